@@ -1,0 +1,236 @@
+/*
+ * cmif.h -- C ABI of libcmif, a gfx950 (MI355X) implementation of the
+ * cross-mutual-information function (CMIF) and of MI-maximising global
+ * alignment over rotations and displacements.
+ *
+ * What is computed (Ofverstedt, Lindblad, Sladoje, "Fast computation of
+ * mutual information in the frequency domain with applications to global
+ * multimodal image alignment"):
+ *   - Sec. 2, Eq. 1-4: mutual information of two label images over their
+ *     common domain, in bits, I = H_A + H_B - H_AB;
+ *   - Eq. 5: CMIF(chi; A, B) = I(A, T_chi[B]) with T_chi[B](x) = B(x + chi);
+ *   - Sec. 3.2, Eq. 8-12: joint counts C_ab(chi) are cross-correlations
+ *     (Eq. 7) of masked level-set indicators, computed with FFTs; counts are
+ *     rounded to integers, so the result equals the direct method's
+ *     (Sec. 3.4); entropies of the relative histograms give the map;
+ *   - Sec. 3.6, Alg. 1: global alignment; for every transform in the set,
+ *     the displacement with the largest CMIF among those whose valid-point
+ *     count N reaches gamma * max N, and across transforms a strictly larger
+ *     value wins.
+ *
+ * Conventions that every entry point shares:
+ *   - Images are row-major, uint8 labels in [0, Q) wherever their mask is
+ *     set; masks are uint8 0/1 (a NULL mask means all ones).
+ *   - Displacements: the full set of chi with a non-empty rectangle overlap,
+ *     chi_y in [-(h_a-1), h_b-1], chi_x in [-(w_a-1), w_b-1].  A map has
+ *     S_h x S_w entries, S_h = h_a + h_b - 1, S_w = w_a + w_b - 1, and entry
+ *     [i][j] holds chi = (i - (h_a-1), j - (w_a-1)).
+ *   - Marginal counts and N are the exact integer sums of the rounded joint
+ *     counts (identical to Eq. 10-11 in exact arithmetic).
+ *   - MI is in bits, 0 where N = 0, with 0 log 0 = 0.
+ *   - Rotation (the transform set Omega): B and M_B are resampled by
+ *     nearest neighbour (Sec. 3.6) about B's centre with a fixed-point rule:
+ *     c = round(cos(theta) 2^16), s = round(sin(theta) 2^16); output pixel
+ *     (y, x) reads B at the source obtained by rotating the doubled centred
+ *     coordinates (2x-(w_b-1), 2y-(h_b-1)) by [[c, -s], [s, c]] and rounding
+ *     half up; a source outside B or on M_B = 0 gives mask 0.  theta = 0 is
+ *     exactly the identity.  A result (angle, chi) means: A's pixel x
+ *     corresponds to B's pixel src_theta(x + chi).
+ *
+ * Ownership and execution:
+ *   - The caller owns every device buffer (inputs, outputs, workspaces).
+ *     The library owns only host-side plan state.
+ *   - Device pointers are HIP device addresses on the plan's device.  The
+ *     stream argument is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Every call only enqueues work on that stream and returns;
+ *     results are valid once the stream has been synchronised.
+ *   - Host-detectable errors (bad arguments, unsupported sizes, workspace
+ *     too small, wrong device) are returned before anything is enqueued.
+ *     Conditions seen on the device (labels >= Q inside a mask, rounding
+ *     residuals, fallbacks, non-finite soft inputs) are reported in
+ *     cmif_stats.
+ *   - No C++ exception crosses the ABI.  A plan is not safe for concurrent
+ *     calls; calls of distinct plans may run concurrently on distinct
+ *     streams with distinct workspaces.
+ */
+#ifndef CMIF_H
+#define CMIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cmif_status {
+  CMIF_OK = 0,
+  CMIF_ERR_INVALID_ARGUMENT = 1,  /* NULL where required, bad sizes, Q, gamma */
+  CMIF_ERR_UNSUPPORTED = 2,       /* valid but not supported (size too big) */
+  CMIF_ERR_WORKSPACE_TOO_SMALL = 3,
+  CMIF_ERR_DEVICE = 4,            /* a HIP runtime call failed */
+  CMIF_ERR_WRONG_MODE = 5,        /* e.g. cmif_backward on a HARD plan */
+  CMIF_ERR_NO_DEVICE = 6,         /* no usable gfx950 device */
+  CMIF_ERR_HOST_MEMORY = 7
+} cmif_status;
+
+/* precision of the FFT stages (Sec. 3.2 "rounding ... to integers") */
+enum {
+  CMIF_PREC_FP32_ROUNDED = 0, /* FP32 FFTs, counts rounded, residual check,
+                                 FP64 re-run of flagged label pairs */
+  CMIF_PREC_FP64 = 1          /* every FFT stage in FP64 */
+};
+
+enum {
+  CMIF_MODE_HARD = 0, /* categorical labels (Eq. 8 level sets) */
+  CMIF_MODE_SOFT = 1  /* real memberships in place of level sets */
+};
+
+enum {
+  /* send every label pair through the FP64 re-run, whatever its residual */
+  CMIF_FLAG_FORCE_FALLBACK = 1u << 0,
+  /* keep the schedule host-visible: one kernel per stage and angle, no
+     graph capture (a debugging aid; results are identical) */
+  CMIF_FLAG_NO_GRAPH = 1u << 1,
+  /* SOFT: keep what cmif_backward needs in the persistent workspace */
+  CMIF_FLAG_SAVE_FOR_BACKWARD = 1u << 2
+};
+
+/* Plan description.  Every pointer is a host pointer read during cmif_plan
+   only. */
+typedef struct cmif_plan_desc {
+  int32_t n_pairs;           /* image pairs handled by one call, >= 1 */
+  const int32_t* h_a;        /* [n_pairs] heights of A, 1..1024 */
+  const int32_t* w_a;        /* [n_pairs] widths of A, 1..1024 */
+  const int32_t* h_b;        /* [n_pairs] heights of B, 1..1024 */
+  const int32_t* w_b;        /* [n_pairs] widths of B, 1..1024 */
+  int32_t q_a;               /* labels of A, 1..64 */
+  int32_t q_b;               /* labels of B, 1..64 */
+  int32_t n_angles;          /* rotation angles applied to B, >= 1 */
+  const double* angles_rad;  /* [n_angles]; NULL means the single angle 0 */
+  double gamma;              /* overlap fraction of Alg. 1, in [0, 1] */
+  int32_t precision;         /* CMIF_PREC_* */
+  int32_t mode;              /* CMIF_MODE_* */
+  uint32_t flags;            /* CMIF_FLAG_* */
+  int32_t device;            /* HIP device ordinal */
+  int32_t angle_batch;       /* angles per pipeline pass, 0 = automatic */
+  int32_t reserved;
+} cmif_plan_desc;
+
+typedef struct cmif_plan_s* cmif_plan_t;
+
+/* Device-side diagnostics, accumulated by every call that is given one
+   (the caller zero-fills it before the first call it wants counted). */
+typedef struct cmif_stats {
+  uint32_t label_errors;      /* pixels inside a mask whose label is >= Q */
+  uint32_t flagged_pairs;     /* (angle, image pair, label pair) items whose
+                                 FP32 rounding residual reached 0.25 */
+  uint32_t fallback_pairs;    /* items recomputed in FP64 */
+  uint32_t fallback_overflow; /* flagged items beyond the re-run capacity */
+  float max_residual;         /* max |y - rint(y)| over used displacements of
+                                 the FP32 stages (before any re-run) */
+  uint32_t nonfinite_inputs;  /* SOFT: NaN/Inf memberships seen */
+  uint32_t reserved[2];
+} cmif_stats;
+
+/* One alignment result (Alg. 1 output): the angle index into the plan's
+   angle list, the displacement, its MI (bits) and its valid-point count. */
+typedef struct cmif_best {
+  int32_t angle_index;
+  int32_t dy;
+  int32_t dx;
+  int32_t reserved;
+  double angle_rad;
+  double mi;
+  int64_t n;
+} cmif_best;
+
+/* Inputs: host arrays with one DEVICE pointer per image pair. */
+typedef struct cmif_inputs {
+  const uint8_t* const* labels_a; /* HARD: [h_a][w_a] labels of A */
+  const uint8_t* const* mask_a;   /* array may be NULL; entries may be NULL */
+  const uint8_t* const* labels_b; /* HARD: [h_b][w_b] labels of B */
+  const uint8_t* const* mask_b;
+  const float* const* memb_a;     /* SOFT: [q_a][h_a][w_a] memberships of A */
+  const float* const* memb_b;     /* SOFT: [q_b][h_b][w_b] memberships of B */
+} cmif_inputs;
+
+/* Outputs of cmif_compute: host arrays (or NULL) with one DEVICE pointer per
+   image pair; each output is written for every angle of the plan. */
+typedef struct cmif_outputs {
+  double* const* mi;       /* [n_angles][S_h][S_w] MI map in bits */
+  int32_t* const* n;       /* HARD: [n_angles][S_h][S_w] valid-point count */
+  int32_t* const* counts;  /* HARD: [n_angles][q_a][q_b][S_h][S_w] joint */
+  uint64_t* const* digest; /* HARD: [n_angles][q_a][q_b] order-free
+                              fingerprint of each joint count map:
+                              sum_chi C_ab(chi) * splitmix64(i*S_w + j)
+                              modulo 2^64 (splitmix64 = Vigna's mixer
+                              applied once to the map index) */
+  cmif_best* best;         /* [n_pairs] Alg. 1 result over all angles */
+  cmif_best* per_angle;    /* [n_pairs][n_angles] best per angle */
+  cmif_stats* stats;       /* one struct, accumulated */
+} cmif_outputs;
+
+/* Builds a plan: validates the description, chooses FFT sizes (smallest
+   power of two >= S per axis, at least 128), workspace layout and angle
+   batching, and computes the fixed-point rotation coefficients.  Touches no
+   device memory.  On success *out owns host memory released by
+   cmif_plan_free.  Errors: CMIF_ERR_INVALID_ARGUMENT (NULL desc/out/size
+   arrays, n_pairs < 1, sizes out of range, Q out of range, gamma outside
+   [0, 1] or NaN, unknown precision/mode/flags), CMIF_ERR_UNSUPPORTED,
+   CMIF_ERR_NO_DEVICE, CMIF_ERR_HOST_MEMORY. */
+cmif_status cmif_plan(const cmif_plan_desc* desc, cmif_plan_t* out);
+
+/* Releases host state; never frees caller memory.  NULL is ignored. */
+void cmif_plan_free(cmif_plan_t plan);
+
+/* Device workspace the caller must provide to cmif_compute / cmif_align /
+   cmif_backward: `persistent` bytes that keep their content between calls
+   of this plan (twiddle and log tables; SOFT forward state for
+   cmif_backward) and `scratch` bytes that the call may overwrite.  Both
+   buffers must be 256-byte aligned device memory of at least these sizes;
+   every call receives the sizes it was given and rejects smaller ones with
+   CMIF_ERR_WORKSPACE_TOO_SMALL before enqueuing anything. */
+cmif_status cmif_workspace_size(cmif_plan_t plan, size_t* persistent,
+                                size_t* scratch);
+
+/* CMIF maps (Eq. 5, Sec. 3.2) for every image pair and angle, plus the
+   Alg. 1 results when out->best / out->per_angle are given.  Any output may
+   be NULL.  HARD plans read labels/masks, SOFT plans memberships/masks (and
+   ignore n, counts and digest). */
+cmif_status cmif_compute(cmif_plan_t plan, const cmif_inputs* in,
+                         const cmif_outputs* out, void* persistent,
+                         size_t persistent_bytes, void* scratch,
+                         size_t scratch_bytes, void* stream);
+
+/* Global alignment (Alg. 1, lines 3-9): best[p] is the result for image
+   pair p over all angles; per_angle (nullable) is [n_pairs][n_angles].
+   No map is written.  stats is nullable. */
+cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
+                       cmif_best* best, cmif_best* per_angle,
+                       cmif_stats* stats, void* persistent,
+                       size_t persistent_bytes, void* scratch,
+                       size_t scratch_bytes, void* stream);
+
+/* SOFT plans with CMIF_FLAG_SAVE_FOR_BACKWARD, after cmif_compute on the
+   same inputs: given dL/dMI (grad_mi[p], device [n_angles][S_h][S_w]
+   double), writes dL/dmemb_a (grad_a[p], [q_a][h_a][w_a] float) and
+   dL/dmemb_b (grad_b[p], [q_b][h_b][w_b] float), overwriting them.  Either
+   output array may be NULL to skip it. */
+cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
+                          const double* const* grad_mi, float* const* grad_a,
+                          float* const* grad_b, void* persistent,
+                          size_t persistent_bytes, void* scratch,
+                          size_t scratch_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* cmif_status_string(cmif_status status);
+
+/* Detail message of the last error returned to this thread ("" if none). */
+const char* cmif_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMIF_H */

@@ -175,13 +175,14 @@ def align(A, MA, B, MB, qa, qb, angles, gamma, nthreads=0, per_angle=False):
     """Alg. 1 (lines 3-9) over the given angles, labels already quantised
     and no zero padding (the full displacement range already contains every
     displacement the padding would admit).  Per angle: warp B and M_B, full
-    direct CMIF map, gamma-constrained argmax; across angles a strictly larger
-    MI replaces the best (the first angle wins ties).
+    direct CMIF map, gamma-constrained argmax; the best starts as the identity
+    with I = 0 (angle_index -1) and a strictly larger MI replaces it, so the
+    first angle wins ties.
     Returns dict(angle_index, angle, dy, dx, mi, n[, per_angle list])."""
     A = _u8(A)
     ha, wa = A.shape
+    # I <- 0, T <- IDENTITY (reported as angle_index -1, displacement 0)
     best = dict(angle_index=-1, angle=0.0, dy=0, dx=0, mi=0.0, n=0)
-    found = False
     rows = []
     for k, th in enumerate(angles):
         bw, mw = warp_nn(B, MB, th)
@@ -192,9 +193,8 @@ def align(A, MA, B, MB, qa, qb, angles, gamma, nthreads=0, per_angle=False):
         rec = dict(angle_index=k, angle=float(th), dy=i - (ha - 1),
                    dx=j - (wa - 1), mi=v, n=nn)
         rows.append(rec)
-        if not found or v > best["mi"]:
+        if v > best["mi"]:
             best = dict(rec)
-            found = True
     if per_angle:
         best["per_angle"] = rows
     return best

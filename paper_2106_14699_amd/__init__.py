@@ -1,0 +1,411 @@
+"""Python binding of libcmif (include/cmif.h), the gfx950 CMIF library.
+
+The functions named like the C entry points (cmif_plan, cmif_workspace_size,
+cmif_compute, cmif_align, cmif_backward, cmif_plan_free, cmif_status_string,
+cmif_last_error) marshal arguments through ctypes and call the library; every
+step of the computation runs in the library's HIP kernels.  `Plan` is a thin
+convenience wrapper that takes torch tensors, allocates the outputs and the
+workspace with torch on the plan's device, and passes torch's current stream.
+
+Importing this module loads libcmif.so and raises if it is missing: there is
+no CPU or PyTorch fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmif.so")
+
+CMIF_OK = 0
+CMIF_ERR_INVALID_ARGUMENT = 1
+CMIF_ERR_UNSUPPORTED = 2
+CMIF_ERR_WORKSPACE_TOO_SMALL = 3
+CMIF_ERR_DEVICE = 4
+CMIF_ERR_WRONG_MODE = 5
+CMIF_ERR_NO_DEVICE = 6
+CMIF_ERR_HOST_MEMORY = 7
+
+CMIF_PREC_FP32_ROUNDED = 0
+CMIF_PREC_FP64 = 1
+CMIF_MODE_HARD = 0
+CMIF_MODE_SOFT = 1
+CMIF_FLAG_FORCE_FALLBACK = 1 << 0
+CMIF_FLAG_NO_GRAPH = 1 << 1
+CMIF_FLAG_SAVE_FOR_BACKWARD = 1 << 2
+
+EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
+            "cmif_compute", "cmif_align", "cmif_backward",
+            "cmif_status_string", "cmif_last_error")
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+
+class cmif_plan_desc(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int32),
+                ("h_a", ctypes.POINTER(ctypes.c_int32)),
+                ("w_a", ctypes.POINTER(ctypes.c_int32)),
+                ("h_b", ctypes.POINTER(ctypes.c_int32)),
+                ("w_b", ctypes.POINTER(ctypes.c_int32)),
+                ("q_a", ctypes.c_int32), ("q_b", ctypes.c_int32),
+                ("n_angles", ctypes.c_int32),
+                ("angles_rad", ctypes.POINTER(ctypes.c_double)),
+                ("gamma", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("angle_batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class cmif_stats(ctypes.Structure):
+    _fields_ = [("label_errors", ctypes.c_uint32),
+                ("flagged_pairs", ctypes.c_uint32),
+                ("fallback_pairs", ctypes.c_uint32),
+                ("fallback_overflow", ctypes.c_uint32),
+                ("max_residual", ctypes.c_float),
+                ("nonfinite_inputs", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
+
+
+class cmif_best(ctypes.Structure):
+    _fields_ = [("angle_index", ctypes.c_int32), ("dy", ctypes.c_int32),
+                ("dx", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("angle_rad", ctypes.c_double), ("mi", ctypes.c_double),
+                ("n", ctypes.c_int64)]
+
+
+class cmif_inputs(ctypes.Structure):
+    _fields_ = [("labels_a", _PP), ("mask_a", _PP), ("labels_b", _PP),
+                ("mask_b", _PP), ("memb_a", _PP), ("memb_b", _PP)]
+
+
+class cmif_outputs(ctypes.Structure):
+    _fields_ = [("mi", _PP), ("n", _PP), ("counts", _PP), ("digest", _PP),
+                ("best", _P), ("per_angle", _P), ("stats", _P)]
+
+
+class CmifError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {cmif_status_string(status)}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libcmif.so not found at {LIB_PATH}; build it with "
+            "`python -m paper_2106_14699_amd.build` (there is no fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    S = ctypes.c_size_t
+    lib.cmif_plan.argtypes = [ctypes.POINTER(cmif_plan_desc), ctypes.POINTER(_P)]
+    lib.cmif_plan.restype = ctypes.c_int
+    lib.cmif_plan_free.argtypes = [_P]
+    lib.cmif_plan_free.restype = None
+    lib.cmif_workspace_size.argtypes = [_P, ctypes.POINTER(S), ctypes.POINTER(S)]
+    lib.cmif_workspace_size.restype = ctypes.c_int
+    lib.cmif_compute.argtypes = [_P, ctypes.POINTER(cmif_inputs),
+                                 ctypes.POINTER(cmif_outputs), _P, S, _P, S, _P]
+    lib.cmif_compute.restype = ctypes.c_int
+    lib.cmif_align.argtypes = [_P, ctypes.POINTER(cmif_inputs), _P, _P, _P, _P,
+                               S, _P, S, _P]
+    lib.cmif_align.restype = ctypes.c_int
+    lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
+                                  _PP, _P, S, _P, S, _P]
+    lib.cmif_backward.restype = ctypes.c_int
+    lib.cmif_status_string.argtypes = [ctypes.c_int]
+    lib.cmif_status_string.restype = ctypes.c_char_p
+    lib.cmif_last_error.argtypes = []
+    lib.cmif_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load_lib()
+
+
+# -- entry points with the C names (marshalling only) ------------------------
+
+def cmif_status_string(status: int) -> str:
+    return _lib.cmif_status_string(int(status)).decode()
+
+
+def cmif_last_error() -> str:
+    return _lib.cmif_last_error().decode()
+
+
+def _check(status: int, where: str):
+    if status != CMIF_OK:
+        raise CmifError(status, where, cmif_last_error())
+
+
+def cmif_plan(desc: cmif_plan_desc) -> int:
+    h = _P()
+    _check(_lib.cmif_plan(ctypes.byref(desc), ctypes.byref(h)), "cmif_plan")
+    return h.value
+
+
+def cmif_plan_free(plan: int) -> None:
+    _lib.cmif_plan_free(_P(plan))
+
+
+def cmif_workspace_size(plan: int) -> tuple[int, int]:
+    p = ctypes.c_size_t()
+    s = ctypes.c_size_t()
+    _check(_lib.cmif_workspace_size(_P(plan), ctypes.byref(p), ctypes.byref(s)),
+           "cmif_workspace_size")
+    return p.value, s.value
+
+
+def cmif_compute(plan, inputs, outputs, persistent, persistent_bytes, scratch,
+                 scratch_bytes, stream) -> None:
+    _check(_lib.cmif_compute(_P(plan), ctypes.byref(inputs),
+                             ctypes.byref(outputs), _P(persistent),
+                             persistent_bytes, _P(scratch), scratch_bytes,
+                             _P(stream)), "cmif_compute")
+
+
+def cmif_align(plan, inputs, best, per_angle, stats, persistent,
+               persistent_bytes, scratch, scratch_bytes, stream) -> None:
+    _check(_lib.cmif_align(_P(plan), ctypes.byref(inputs), _P(best),
+                           _P(per_angle), _P(stats), _P(persistent),
+                           persistent_bytes, _P(scratch), scratch_bytes,
+                           _P(stream)), "cmif_align")
+
+
+def cmif_backward(plan, inputs, grad_mi, grad_a, grad_b, persistent,
+                  persistent_bytes, scratch, scratch_bytes, stream) -> None:
+    _check(_lib.cmif_backward(_P(plan), ctypes.byref(inputs), grad_mi, grad_a,
+                              grad_b, _P(persistent), persistent_bytes,
+                              _P(scratch), scratch_bytes, _P(stream)),
+           "cmif_backward")
+
+
+# -- torch convenience layer ----------------------------------------------------
+
+def _ptr_array(ptrs):
+    if ptrs is None:
+        return None
+    arr = (ctypes.c_void_p * len(ptrs))(*[p if p else None for p in ptrs])
+    return ctypes.cast(arr, _PP), arr
+
+
+BEST_DTYPE_FIELDS = ("angle_index", "dy", "dx", "reserved", "angle_rad", "mi",
+                     "n")
+
+
+def best_from_bytes(raw: bytes) -> dict:
+    b = cmif_best.from_buffer_copy(raw)
+    return {k: getattr(b, k) for k in BEST_DTYPE_FIELDS if k != "reserved"}
+
+
+class Plan:
+    """A plan for n image pairs (sizes given per pair) with fixed Q_A, Q_B,
+    angle list and gamma.  Tensors passed in must live on the plan's device
+    (uint8 labels/masks, row-major)."""
+
+    def __init__(self, sizes: Sequence[tuple[int, int, int, int]], q_a: int,
+                 q_b: int, angles: Sequence[float] | None = None,
+                 gamma: float = 0.5, precision: str = "fp32",
+                 mode: str = "hard", flags: int = 0, device: int = 0,
+                 angle_batch: int = 0):
+        import torch
+        self._torch = torch
+        self.sizes = [tuple(int(v) for v in s) for s in sizes]
+        n = len(self.sizes)
+        self.q_a, self.q_b = int(q_a), int(q_b)
+        self.angles = [0.0] if angles is None else [float(a) for a in angles]
+        self.gamma = float(gamma)
+        self.device = int(device)
+        i32 = ctypes.c_int32 * n
+        self._keep = [i32(*[s[k] for s in self.sizes]) for k in range(4)]
+        ang = (ctypes.c_double * len(self.angles))(*self.angles)
+        self._keep.append(ang)
+        d = cmif_plan_desc()
+        d.n_pairs = n
+        d.h_a, d.w_a, d.h_b, d.w_b = [ctypes.cast(a, ctypes.POINTER(ctypes.c_int32))
+                                      for a in self._keep[:4]]
+        d.q_a, d.q_b = self.q_a, self.q_b
+        d.n_angles = len(self.angles)
+        d.angles_rad = ctypes.cast(ang, ctypes.POINTER(ctypes.c_double))
+        d.gamma = self.gamma
+        d.precision = {"fp32": CMIF_PREC_FP32_ROUNDED,
+                       "fp64": CMIF_PREC_FP64}[precision]
+        d.mode = {"hard": CMIF_MODE_HARD, "soft": CMIF_MODE_SOFT}[mode]
+        d.flags = int(flags)
+        d.device = self.device
+        d.angle_batch = int(angle_batch)
+        self.handle = cmif_plan(d)
+        self.persistent_bytes, self.scratch_bytes = cmif_workspace_size(
+            self.handle)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            cmif_plan_free(h)
+            self.handle = None
+
+    def map_shape(self, p: int = 0):
+        ha, wa, hb, wb = self.sizes[p]
+        return ha + hb - 1, wa + wb - 1
+
+    def _aligned(self, nbytes: int):
+        torch = self._torch
+        buf = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8,
+                          device=f"cuda:{self.device}")
+        off = (-buf.data_ptr()) % 256
+        return buf, buf.data_ptr() + off
+
+    def workspace(self):
+        if self._ws is None:
+            pb, pp = self._aligned(self.persistent_bytes)
+            sb, sp = self._aligned(self.scratch_bytes)
+            self._ws = (pb, pp, sb, sp)
+        return self._ws
+
+    def _inputs(self, A, MA, B, MB):
+        A, B = _listify(A), _listify(B)
+        MA, MB = _listify(MA, len(A)), _listify(MB, len(B))
+        n = len(self.sizes)
+        if len(A) != n or len(B) != n:
+            raise ValueError("one A and one B per image pair")
+        for p in range(n):
+            ha, wa, hb, wb = self.sizes[p]
+            _check_tensor(A[p], (ha, wa), self.device, "A")
+            _check_tensor(B[p], (hb, wb), self.device, "B")
+            if MA[p] is not None:
+                _check_tensor(MA[p], (ha, wa), self.device, "MA")
+            if MB[p] is not None:
+                _check_tensor(MB[p], (hb, wb), self.device, "MB")
+        keep = []
+        inp = cmif_inputs()
+        for name, ts in (("labels_a", A), ("mask_a", MA), ("labels_b", B),
+                         ("mask_b", MB)):
+            ptrs = [t.data_ptr() if t is not None else 0 for t in ts]
+            pa, arr = _ptr_array(ptrs)
+            keep.append(arr)
+            setattr(inp, name, pa)
+        return inp, keep
+
+    def _stream(self):
+        return self._torch.cuda.current_stream(self.device).cuda_stream
+
+    def compute(self, A, MA=None, B=None, MB=None, *, mi=True, n=True,
+                counts=False, digest=False, best=False, per_angle=False):
+        """CMIF maps for every pair and angle.  Returns a dict of lists (one
+        entry per pair) of torch tensors, plus 'stats' (dict)."""
+        torch = self._torch
+        inp, keep = self._inputs(A, MA, B, MB)
+        dev = f"cuda:{self.device}"
+        na = len(self.angles)
+        res = {}
+        outs = cmif_outputs()
+        for name, want, dtype, shape_fn in (
+                ("mi", mi, torch.float64, lambda s: (na, *s)),
+                ("n", n, torch.int32, lambda s: (na, *s)),
+                ("counts", counts, torch.int32,
+                 lambda s: (na, self.q_a, self.q_b, *s)),
+                ("digest", digest, torch.int64,
+                 lambda s: (na, self.q_a, self.q_b))):
+            if want:
+                ts = [torch.empty(shape_fn(self.map_shape(p)), dtype=dtype,
+                                  device=dev) for p in range(len(self.sizes))]
+                res[name] = ts
+                pa, arr = _ptr_array([t.data_ptr() for t in ts])
+                keep.append(arr)
+                setattr(outs, name, pa)
+        nbest = ctypes.sizeof(cmif_best)
+        best_t = torch.empty((len(self.sizes), nbest), dtype=torch.uint8,
+                             device=dev) if best else None
+        pa_t = torch.empty((len(self.sizes), na, nbest), dtype=torch.uint8,
+                           device=dev) if per_angle else None
+        stats_t = torch.zeros(ctypes.sizeof(cmif_stats), dtype=torch.uint8,
+                              device=dev)
+        outs.best = best_t.data_ptr() if best else None
+        outs.per_angle = pa_t.data_ptr() if per_angle else None
+        outs.stats = stats_t.data_ptr()
+        pb, pp, sb, sp = self.workspace()
+        cmif_compute(self.handle, inp, outs, pp, self.persistent_bytes, sp,
+                     self.scratch_bytes, self._stream())
+        torch.cuda.current_stream(self.device).synchronize()
+        res["stats"] = _stats_dict(stats_t)
+        if best:
+            res["best"] = [best_from_bytes(bytes(best_t[p].cpu().numpy()))
+                           for p in range(len(self.sizes))]
+        if per_angle:
+            raw = pa_t.cpu().numpy()
+            res["per_angle"] = [[best_from_bytes(bytes(raw[p, k]))
+                                 for k in range(na)]
+                                for p in range(len(self.sizes))]
+        del keep
+        return res
+
+    def align(self, A, MA=None, B=None, MB=None, *, per_angle=False,
+              sync=True):
+        """Alg. 1 over the plan's angles for every pair.  Returns a list of
+        best dicts (and per-angle lists), plus stats."""
+        torch = self._torch
+        inp, keep = self._inputs(A, MA, B, MB)
+        dev = f"cuda:{self.device}"
+        na = len(self.angles)
+        nbest = ctypes.sizeof(cmif_best)
+        best_t = torch.empty((len(self.sizes), nbest), dtype=torch.uint8,
+                             device=dev)
+        pa_t = torch.empty((len(self.sizes), na, nbest), dtype=torch.uint8,
+                           device=dev) if per_angle else None
+        stats_t = torch.zeros(ctypes.sizeof(cmif_stats), dtype=torch.uint8,
+                              device=dev)
+        pb, pp, sb, sp = self.workspace()
+        cmif_align(self.handle, inp, best_t.data_ptr(),
+                   pa_t.data_ptr() if per_angle else None, stats_t.data_ptr(),
+                   pp, self.persistent_bytes, sp, self.scratch_bytes,
+                   self._stream())
+        del keep
+        if not sync:
+            return dict(best_raw=best_t, per_angle_raw=pa_t, stats_raw=stats_t)
+        torch.cuda.current_stream(self.device).synchronize()
+        res = dict(best=[best_from_bytes(bytes(best_t[p].cpu().numpy()))
+                         for p in range(len(self.sizes))],
+                   stats=_stats_dict(stats_t))
+        if per_angle:
+            raw = pa_t.cpu().numpy()
+            res["per_angle"] = [[best_from_bytes(bytes(raw[p, k]))
+                                 for k in range(na)]
+                                for p in range(len(self.sizes))]
+        return res
+
+
+def _listify(x, n=None):
+    if isinstance(x, (list, tuple)):
+        return list(x)
+    if x is None:
+        return [None] * (n or 1)
+    return [x]
+
+
+def _check_tensor(t, shape, device, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.uint8 or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be uint8 of shape {shape}, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stats_dict(stats_t):
+    s = cmif_stats.from_buffer_copy(bytes(stats_t.cpu().numpy()))
+    return dict(label_errors=s.label_errors, flagged_pairs=s.flagged_pairs,
+                fallback_pairs=s.fallback_pairs,
+                fallback_overflow=s.fallback_overflow,
+                max_residual=s.max_residual,
+                nonfinite_inputs=s.nonfinite_inputs)

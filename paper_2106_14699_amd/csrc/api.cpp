@@ -1,0 +1,540 @@
+// C ABI of libcmif: plan construction, workspace layout, host validation and
+// the per-pair schedule of kernels (hard labels, FP32-rounded or FP64).
+//
+// Schedule for one image pair (all on the caller's stream):
+//   tables      twiddles exp(2 pi i t/P) for each FFT length, log2 table
+//   check       labels >= Q inside a mask -> stats.label_errors
+//   A forward   rows (identity resampling) -> columns: F_A[label][c][k_y]
+//   per batch of angles:
+//     B forward rows (fixed-point NN rotation fused) -> columns
+//     pair columns   conj(F_A,a) F_B,b and inverse FFT along y -> Z
+//     pair rows      inverse FFT along x, rounding, residual check, fused
+//                    entropy sums -> MI map, N map, max N, flags
+//     argmax         gamma-eligible argmax per angle, running best (Alg. 1)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace cmif;
+
+namespace {
+
+thread_local std::string g_err;
+
+cmif_status fail(cmif_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int pow2_at_least(int v) {
+  int p = kMinP;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+struct PairPlan {
+  int ha, wa, hb, wb, sh, sw, ph, pw;
+};
+
+struct ScratchLayout {
+  size_t xa, fa, xb, fb, z, mi, n, maxn, flags, partial, running, stats, end;
+};
+
+}  // namespace
+
+struct cmif_plan_s {
+  cmif_plan_desc d;
+  std::vector<PairPlan> pairs;
+  std::vector<double> angles;
+  std::vector<int32_t> rc, rs;
+  int batch = 1;
+  std::vector<int> plens;       // distinct FFT lengths
+  std::vector<size_t> tw_off;   // per plens entry: FP32 table, FP64 follows
+  size_t logtab_off = 0;
+  size_t persistent_bytes = 0;
+  ScratchLayout lay{};
+  size_t scratch_bytes = 0;
+  int nchunks_max = 1;
+  bool device_checked = false;
+};
+
+namespace {
+
+size_t elem_bytes(const cmif_plan_s& P) {
+  return P.d.precision == CMIF_PREC_FP64 ? sizeof(double2) : sizeof(float2);
+}
+
+int rows_per_chunk(int sh) { return (sh + 63) / 64; }
+
+ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
+  const size_t E = elem_bytes(P);
+  const size_t qa = P.d.q_a, qb = P.d.q_b, nb = P.batch;
+  const size_t half = g.pw / 2;
+  ScratchLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += up256(bytes); return r; };
+  L.xa = take(qa * half * g.ha * E);
+  L.fa = take(qa * half * g.ph * E);
+  L.xb = take(nb * qb * half * g.hb * E);
+  L.fb = take(nb * qb * half * g.ph * E);
+  L.z = take(nb * qa * qb * half * g.sh * E);
+  L.mi = take(nb * (size_t)g.sh * g.sw * sizeof(double));
+  L.n = take(nb * (size_t)g.sh * g.sw * sizeof(int32_t));
+  L.maxn = take(nb * sizeof(uint32_t));
+  L.flags = take(nb * qa * qb * sizeof(uint32_t));
+  const int nchunks = (g.sh + rows_per_chunk(g.sh) - 1) / rows_per_chunk(g.sh);
+  L.partial = take(nb * nchunks * sizeof(ArgPartial));
+  L.running = take(sizeof(cmif_best));
+  L.stats = take(sizeof(cmif_stats));
+  L.end = o;
+  return L;
+}
+
+int find_plen(const cmif_plan_s& P, int p) {
+  for (size_t i = 0; i < P.plens.size(); ++i)
+    if (P.plens[i] == p) return (int)i;
+  return -1;
+}
+
+cmif_status check_device(cmif_plan_s* P) {
+  if (P->device_checked) return CMIF_OK;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(CMIF_ERR_NO_DEVICE, "no HIP device");
+  if (P->d.device < 0 || P->d.device >= n)
+    return fail(CMIF_ERR_NO_DEVICE, "device ordinal out of range");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, P->d.device) != hipSuccess)
+    return fail(CMIF_ERR_DEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(CMIF_ERR_NO_DEVICE,
+                std::string("libcmif is built for gfx950, device is ") +
+                    prop.gcnArchName);
+  P->device_checked = true;
+  return CMIF_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess) {
+      ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIP_TRY(expr)                                                       \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess)                                                   \
+      return fail(CMIF_ERR_DEVICE, std::string(#expr) + ": " +              \
+                                       hipGetErrorString(_e));              \
+  } while (0)
+
+struct CallOutputs {
+  double* mi = nullptr;          // caller map for this pair or null
+  int32_t* n = nullptr;
+  int32_t* counts = nullptr;
+  uint64_t* digest = nullptr;
+  cmif_best* best = nullptr;
+  cmif_best* per_angle = nullptr;  // [n_angles] for this pair
+  cmif_stats* stats = nullptr;
+};
+
+template <typename T>
+cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
+                     const uint8_t* ma, const uint8_t* lb, const uint8_t* mb,
+                     const CallOutputs& o, uint8_t* pers, uint8_t* scr,
+                     hipStream_t st) {
+  using CT = C2<T>;
+  const PairPlan& g = P.pairs[p];
+  const ScratchLayout L = layout_for(P, g);
+  const int qa = P.d.q_a, qb = P.d.q_b;
+  const int half = g.pw / 2;
+  const int TW = tile_width<T>();
+  const int tiles = half / TW;
+  const bool fp64 = sizeof(T) == 8;
+  const int iw = find_plen(P, g.pw), ih = find_plen(P, g.ph);
+  const CT* tw_w = reinterpret_cast<const CT*>(
+      pers + P.tw_off[iw] + (fp64 ? (size_t)g.pw * sizeof(float2) : 0));
+  const CT* tw_h = reinterpret_cast<const CT*>(
+      pers + P.tw_off[ih] + (fp64 ? (size_t)g.ph * sizeof(float2) : 0));
+  const double* logtab = reinterpret_cast<const double*>(pers + P.logtab_off);
+  CT* xa = reinterpret_cast<CT*>(scr + L.xa);
+  CT* fa = reinterpret_cast<CT*>(scr + L.fa);
+  CT* xb = reinterpret_cast<CT*>(scr + L.xb);
+  CT* fb = reinterpret_cast<CT*>(scr + L.fb);
+  CT* z = reinterpret_cast<CT*>(scr + L.z);
+  double* mi_s = reinterpret_cast<double*>(scr + L.mi);
+  int32_t* n_s = reinterpret_cast<int32_t*>(scr + L.n);
+  uint32_t* maxn = reinterpret_cast<uint32_t*>(scr + L.maxn);
+  uint32_t* flags = reinterpret_cast<uint32_t*>(scr + L.flags);
+  ArgPartial* partial = reinterpret_cast<ArgPartial*>(scr + L.partial);
+  cmif_best* running = reinterpret_cast<cmif_best*>(scr + L.running);
+  cmif_stats* stats = o.stats;
+
+  HIP_TRY(launch_check_labels(la, ma, (long long)g.ha * g.wa, qa, stats, st));
+  HIP_TRY(launch_check_labels(lb, mb, (long long)g.hb * g.wb, qb, stats, st));
+
+  // forward transforms of A's level sets (identity resampling)
+  {
+    FwdRowsArgs<T> a{};
+    a.lab = la; a.msk = ma; a.H = g.ha; a.W = g.wa; a.Q = qa; a.nb = 1;
+    a.rot.c[0] = 65536; a.rot.s[0] = 0;
+    a.xrow = xa; a.angle_stride = 0; a.tw = tw_w;
+    HIP_TRY(launch_fwd_rows<T>(g.pw, a, st));
+    FwdColsArgs<T> c{};
+    c.xrow = xa; c.H = g.ha; c.tiles = tiles; c.Q = qa; c.nb = 1;
+    c.x_angle_stride = 0; c.x_label_stride = (long long)half * g.ha;
+    c.F = fa; c.f_angle_stride = 0; c.f_label_stride = (long long)half * g.ph;
+    c.tw = tw_h;
+    HIP_TRY(launch_fwd_cols<T>(g.ph, c, st));
+  }
+  const int nang = (int)P.angles.size();
+  const long long map_stride = (long long)g.sh * g.sw;
+  const int rpc = rows_per_chunk(g.sh);
+  const int nchunks = (g.sh + rpc - 1) / rpc;
+  const bool want_best = o.best != nullptr || o.per_angle != nullptr;
+  for (int a0 = 0; a0 < nang; a0 += P.batch) {
+    const int nb = std::min(P.batch, nang - a0);
+    FwdRowsArgs<T> r{};
+    r.lab = lb; r.msk = mb; r.H = g.hb; r.W = g.wb; r.Q = qb; r.nb = nb;
+    for (int b = 0; b < nb; ++b) { r.rot.c[b] = P.rc[a0 + b]; r.rot.s[b] = P.rs[a0 + b]; }
+    r.xrow = xb; r.angle_stride = (long long)qb * half * g.hb; r.tw = tw_w;
+    HIP_TRY(launch_fwd_rows<T>(g.pw, r, st));
+    FwdColsArgs<T> c{};
+    c.xrow = xb; c.H = g.hb; c.tiles = tiles; c.Q = qb; c.nb = nb;
+    c.x_angle_stride = (long long)qb * half * g.hb;
+    c.x_label_stride = (long long)half * g.hb;
+    c.F = fb; c.f_angle_stride = (long long)qb * half * g.ph;
+    c.f_label_stride = (long long)half * g.ph; c.tw = tw_h;
+    HIP_TRY(launch_fwd_cols<T>(g.ph, c, st));
+
+    HIP_TRY(launch_fill_u32(maxn, 0u, nb, st));
+    HIP_TRY(launch_fill_u32(flags, 0u, (long long)nb * qa * qb, st));
+
+    PairColsArgs<T> pc{};
+    pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
+    pc.FB = fb; pc.fb_angle_stride = (long long)qb * half * g.ph;
+    pc.fb_label_stride = (long long)half * g.ph;
+    pc.QA = qa; pc.QB = qb; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+    pc.tiles = tiles; pc.nb = nb; pc.Z = z;
+    pc.z_angle_stride = (long long)qa * qb * half * g.sh;
+    pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h;
+    HIP_TRY(launch_pair_cols<T>(g.ph, pc, st));
+
+    double* mi_ptr = o.mi ? o.mi + a0 * map_stride : mi_s;
+    int32_t* n_ptr = o.n ? o.n + a0 * map_stride : n_s;
+    PairRowsArgs<T> pr{};
+    pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
+    pr.QA = qa; pr.QB = qb; pr.wa = g.wa; pr.wb = g.wb;
+    pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb; pr.tw = tw_w;
+    pr.logtab = logtab; pr.mi = mi_ptr; pr.mi_angle_stride = map_stride;
+    pr.n = n_ptr; pr.n_angle_stride = map_stride; pr.maxn = maxn; pr.flags = flags;
+    pr.stats = stats;
+    HIP_TRY(launch_pair_rows<T>(g.pw, pr, st));
+    if (o.counts || o.digest) {
+      PairCountsArgs<T> pk{};
+      pk.Z = z; pk.z_angle_stride = pc.z_angle_stride; pk.z_pair_stride = pc.z_pair_stride;
+      pk.QA = qa; pk.QB = qb; pk.wa = g.wa; pk.wb = g.wb; pk.sh = g.sh; pk.sw = g.sw;
+      pk.ph = g.ph; pk.nb = nb; pk.tw = tw_w;
+      pk.counts = o.counts ? o.counts + (long long)a0 * qa * qb * map_stride : nullptr;
+      pk.counts_angle_stride = (long long)qa * qb * map_stride;
+      pk.digest = o.digest ? o.digest + (long long)a0 * qa * qb : nullptr;
+      HIP_TRY(launch_pair_counts<T>(g.pw, pk, st));
+    }
+
+    if (want_best) {
+      ArgmaxArgs am{};
+      am.mi = mi_ptr; am.n = n_ptr; am.angle_stride = map_stride; am.maxn = maxn;
+      am.sh = g.sh; am.sw = g.sw; am.nb = nb; am.rows_per_chunk = rpc;
+      am.nchunks = nchunks; am.gamma = P.d.gamma; am.partial = partial;
+      HIP_TRY(launch_argmax(am, st));
+      ArgmaxFinalArgs af{};
+      af.partial = partial; af.nb = nb; af.nchunks = nchunks; af.sw = g.sw;
+      af.ha = g.ha; af.wa = g.wa; af.angle0 = a0;
+      for (int b = 0; b < nb; ++b) af.angles[b] = P.angles[a0 + b];
+      af.per_angle = o.per_angle; af.running = running;
+      af.first_batch = a0 == 0; af.best_out = o.best;
+      af.last_batch = a0 + nb >= nang;
+      HIP_TRY(launch_argmax_final(af, st));
+    }
+  }
+  return CMIF_OK;
+}
+
+cmif_status validate_ws(const cmif_plan_s* P, void* pers, size_t pers_bytes,
+                        void* scr, size_t scr_bytes) {
+  if (pers_bytes < P->persistent_bytes || scr_bytes < P->scratch_bytes)
+    return fail(CMIF_ERR_WORKSPACE_TOO_SMALL,
+                "workspace too small: need persistent " +
+                    std::to_string(P->persistent_bytes) + ", scratch " +
+                    std::to_string(P->scratch_bytes));
+  if ((P->persistent_bytes && pers == nullptr) ||
+      (P->scratch_bytes && scr == nullptr))
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "workspace pointer is NULL");
+  if ((reinterpret_cast<uintptr_t>(pers) & 255) ||
+      (reinterpret_cast<uintptr_t>(scr) & 255))
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  return CMIF_OK;
+}
+
+cmif_status run_hard(cmif_plan_s* P, const cmif_inputs* in,
+                     const cmif_outputs* out, cmif_best* best,
+                     cmif_best* per_angle, cmif_stats* stats, void* pers,
+                     void* scr, hipStream_t st) {
+  const int np = P->d.n_pairs;
+  if (in->labels_a == nullptr || in->labels_b == nullptr)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "labels arrays are NULL");
+  for (int p = 0; p < np; ++p)
+    if (in->labels_a[p] == nullptr || in->labels_b[p] == nullptr)
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "label pointer of a pair is NULL");
+  uint8_t* pb = static_cast<uint8_t*>(pers);
+  uint8_t* sb = static_cast<uint8_t*>(scr);
+  // tables
+  for (size_t i = 0; i < P->plens.size(); ++i) {
+    const int L = P->plens[i];
+    HIP_TRY(launch_init_tables(pb + P->tw_off[i],
+                               pb + P->tw_off[i] + (size_t)L * sizeof(float2), L,
+                               i == 0 ? reinterpret_cast<double*>(pb + P->logtab_off)
+                                      : nullptr,
+                               st));
+  }
+  const int nang = (int)P->angles.size();
+  if (out && out->digest) {
+    for (int p = 0; p < np; ++p)
+      if (out->digest[p])
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(out->digest[p]), 0u,
+                                2LL * nang * P->d.q_a * P->d.q_b, st));
+  }
+  for (int p = 0; p < np; ++p) {
+    CallOutputs o;
+    if (out) {
+      o.mi = out->mi ? out->mi[p] : nullptr;
+      o.n = out->n ? out->n[p] : nullptr;
+      o.counts = out->counts ? out->counts[p] : nullptr;
+      o.digest = out->digest ? out->digest[p] : nullptr;
+    }
+    o.best = best ? best + p : nullptr;
+    o.per_angle = per_angle ? per_angle + (size_t)p * nang : nullptr;
+    o.stats = stats;
+    const uint8_t* ma = in->mask_a ? in->mask_a[p] : nullptr;
+    const uint8_t* mb = in->mask_b ? in->mask_b[p] : nullptr;
+    cmif_status s;
+    if (P->d.precision == CMIF_PREC_FP64)
+      s = run_pair<double>(*P, p, in->labels_a[p], ma, in->labels_b[p], mb, o,
+                           pb, sb, st);
+    else
+      s = run_pair<float>(*P, p, in->labels_a[p], ma, in->labels_b[p], mb, o, pb,
+                          sb, st);
+    if (s != CMIF_OK) return s;
+  }
+  return CMIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cmif_status_string(cmif_status s) {
+  switch (s) {
+    case CMIF_OK: return "success";
+    case CMIF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case CMIF_ERR_UNSUPPORTED: return "unsupported configuration";
+    case CMIF_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case CMIF_ERR_DEVICE: return "HIP runtime error";
+    case CMIF_ERR_WRONG_MODE: return "call does not match the plan's mode";
+    case CMIF_ERR_NO_DEVICE: return "no usable gfx950 device";
+    case CMIF_ERR_HOST_MEMORY: return "host memory allocation failed";
+  }
+  return "unknown status";
+}
+
+const char* cmif_last_error(void) { return g_err.c_str(); }
+
+cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
+  g_err.clear();
+  if (out == nullptr) return fail(CMIF_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (d == nullptr) return fail(CMIF_ERR_INVALID_ARGUMENT, "desc is NULL");
+  if (d->n_pairs < 1)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "n_pairs must be >= 1");
+  if (!d->h_a || !d->w_a || !d->h_b || !d->w_b)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "size arrays must not be NULL");
+  if (d->q_a < 1 || d->q_a > 64 || d->q_b < 1 || d->q_b > 64)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "q_a and q_b must be in [1, 64]");
+  if (!(d->gamma >= 0.0 && d->gamma <= 1.0))
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "gamma must be in [0, 1]");
+  if (d->precision != CMIF_PREC_FP32_ROUNDED && d->precision != CMIF_PREC_FP64)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown precision");
+  if (d->mode != CMIF_MODE_HARD && d->mode != CMIF_MODE_SOFT)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown mode");
+  const uint32_t known = CMIF_FLAG_FORCE_FALLBACK | CMIF_FLAG_NO_GRAPH |
+                         CMIF_FLAG_SAVE_FOR_BACKWARD;
+  if (d->flags & ~known) return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown flags");
+  if (d->n_angles < 1)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "n_angles must be >= 1");
+  if (d->angles_rad == nullptr && d->n_angles != 1)
+    return fail(CMIF_ERR_INVALID_ARGUMENT,
+                "angles_rad may be NULL only with n_angles = 1");
+  if (d->angle_batch < 0)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "angle_batch must be >= 0");
+  if (d->mode == CMIF_MODE_SOFT)
+    return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
+
+  cmif_plan_s* P = new (std::nothrow) cmif_plan_s();
+  if (!P) return fail(CMIF_ERR_HOST_MEMORY, "plan allocation failed");
+  P->d = *d;
+  P->d.h_a = P->d.w_a = P->d.h_b = P->d.w_b = nullptr;
+  P->d.angles_rad = nullptr;
+  for (int p = 0; p < d->n_pairs; ++p) {
+    PairPlan g{};
+    g.ha = d->h_a[p]; g.wa = d->w_a[p]; g.hb = d->h_b[p]; g.wb = d->w_b[p];
+    if (g.ha < 1 || g.wa < 1 || g.hb < 1 || g.wb < 1 || g.ha > 1024 ||
+        g.wa > 1024 || g.hb > 1024 || g.wb > 1024) {
+      delete P;
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be in [1, 1024]");
+    }
+    g.sh = g.ha + g.hb - 1;
+    g.sw = g.wa + g.wb - 1;
+    g.ph = pow2_at_least(g.sh);
+    g.pw = pow2_at_least(g.sw);
+    if (g.ph > kMaxP || g.pw > kMaxP) {
+      delete P;
+      return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 2048");
+    }
+    PairRowsConfig rc;
+    const size_t er = d->precision == CMIF_PREC_FP64 ? sizeof(double) : sizeof(float);
+    if (!pair_rows_config(er, g.pw, d->q_b, &rc)) {
+      delete P;
+      return fail(CMIF_ERR_UNSUPPORTED,
+                  "q_b too large for the row kernel at this FFT length");
+    }
+    P->pairs.push_back(g);
+    for (int len : {g.ph, g.pw})
+      if (find_plen(*P, len) < 0) P->plens.push_back(len);
+  }
+  for (int a = 0; a < d->n_angles; ++a) {
+    const double th = d->angles_rad ? d->angles_rad[a] : 0.0;
+    if (!std::isfinite(th)) {
+      delete P;
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "angles must be finite");
+    }
+    P->angles.push_back(th);
+    P->rc.push_back((int32_t)std::llround(std::cos(th) * 65536.0));
+    P->rs.push_back((int32_t)std::llround(std::sin(th) * 65536.0));
+  }
+  // angle batch: keep the pair intermediates of one pass within 8 GiB
+  size_t zmax = 0;
+  const size_t E = elem_bytes(*P);
+  for (const auto& g : P->pairs) {
+    const size_t zb = (size_t)d->q_a * d->q_b * (g.pw / 2) * g.sh * E;
+    zmax = std::max(zmax, zb);
+  }
+  int batch = d->angle_batch;
+  if (batch == 0) {
+    const size_t budget = size_t(8) << 30;
+    batch = (int)std::max<size_t>(1, budget / std::max<size_t>(zmax, 1));
+  }
+  batch = std::min(batch, kMaxBatch);
+  batch = std::min(batch, d->n_angles);
+  P->batch = std::max(batch, 1);
+  // persistent: per FFT length FP32 + FP64 twiddles, then the log table
+  size_t o = 0;
+  for (int len : P->plens) {
+    P->tw_off.push_back(o);
+    o += up256((size_t)len * (sizeof(float2) + sizeof(double2)));
+  }
+  P->logtab_off = o;
+  o += up256(512 * sizeof(double));
+  P->persistent_bytes = o;
+  size_t smax = 0;
+  for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);
+  P->scratch_bytes = smax;
+  *out = P;
+  return CMIF_OK;
+}
+
+void cmif_plan_free(cmif_plan_t plan) { delete plan; }
+
+cmif_status cmif_workspace_size(cmif_plan_t plan, size_t* persistent,
+                                 size_t* scratch) {
+  g_err.clear();
+  if (!plan || !persistent || !scratch)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL argument");
+  *persistent = plan->persistent_bytes;
+  *scratch = plan->scratch_bytes;
+  return CMIF_OK;
+}
+
+cmif_status cmif_compute(cmif_plan_t plan, const cmif_inputs* in,
+                         const cmif_outputs* out, void* persistent,
+                         size_t persistent_bytes, void* scratch,
+                         size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  if (!plan || !in) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan or inputs");
+  cmif_status s = validate_ws(plan, persistent, persistent_bytes, scratch,
+                              scratch_bytes);
+  if (s != CMIF_OK) return s;
+  if (plan->d.mode != CMIF_MODE_HARD)
+    return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
+  s = check_device(plan);
+  if (s != CMIF_OK) return s;
+  DeviceGuard dg(plan->d.device);
+  if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
+  return run_hard(plan, in, out, out ? out->best : nullptr,
+                  out ? out->per_angle : nullptr, out ? out->stats : nullptr,
+                  persistent, scratch, static_cast<hipStream_t>(stream));
+}
+
+cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
+                       cmif_best* best, cmif_best* per_angle,
+                       cmif_stats* stats, void* persistent,
+                       size_t persistent_bytes, void* scratch,
+                       size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  if (!plan || !in) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan or inputs");
+  if (!best) return fail(CMIF_ERR_INVALID_ARGUMENT, "best is NULL");
+  cmif_status s = validate_ws(plan, persistent, persistent_bytes, scratch,
+                              scratch_bytes);
+  if (s != CMIF_OK) return s;
+  if (plan->d.mode != CMIF_MODE_HARD)
+    return fail(CMIF_ERR_WRONG_MODE, "cmif_align needs a HARD plan");
+  s = check_device(plan);
+  if (s != CMIF_OK) return s;
+  DeviceGuard dg(plan->d.device);
+  if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
+  return run_hard(plan, in, nullptr, best, per_angle, stats, persistent,
+                  scratch, static_cast<hipStream_t>(stream));
+}
+
+cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
+                          const double* const* grad_mi, float* const* grad_a,
+                          float* const* grad_b, void* persistent,
+                          size_t persistent_bytes, void* scratch,
+                          size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  (void)in; (void)grad_mi; (void)grad_a; (void)grad_b; (void)persistent;
+  (void)persistent_bytes; (void)scratch; (void)scratch_bytes; (void)stream;
+  if (!plan) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan");
+  if (plan->d.mode != CMIF_MODE_SOFT ||
+      !(plan->d.flags & CMIF_FLAG_SAVE_FOR_BACKWARD))
+    return fail(CMIF_ERR_WRONG_MODE,
+                "cmif_backward needs a SOFT plan with SAVE_FOR_BACKWARD");
+  return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
+}
+
+}  // extern "C"

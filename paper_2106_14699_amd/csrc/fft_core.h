@@ -1,0 +1,198 @@
+// Team-level Stockham FFT for gfx950 (wave64).
+//
+// A "team" of TEAM lanes (one wave, or several waves of one workgroup)
+// transforms one complex sequence of length N = TEAM * R held in registers:
+// lane l owns elements l + TEAM*q, q in [0, R), on entry and on exit
+// (natural order).  Each radix stage does R/r radix-r butterflies per lane in
+// registers; consecutive stages exchange data through a padded LDS buffer.
+// The stage formula is the Stockham autosort recurrence: butterfly j reads
+// elements j + m*N/r, multiplies by w^(m*(j mod Ns)*N/(Ns*r)), and writes
+// output m to (j - j mod Ns)*r + (j mod Ns) + m*Ns.  With the lane mapping
+// above, the reads of every stage are exactly the lane's own registers, and
+// the last stage lands in natural order without an exchange.
+//
+// Radices are chosen greedily, r = min(16, R, N/Ns), so N = 1024 runs as
+// 16 x 16 x 4 with two LDS exchanges.  Twiddles come from a table
+// tw[t] = exp(+2 pi i t / N) computed in FP64 (no recurrences); DIR = -1
+// (forward) uses its conjugate.  Transforms are unnormalised both ways.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmif {
+
+template <typename T> struct c2t;
+template <> struct c2t<float> { using type = float2; };
+template <> struct c2t<double> { using type = double2; };
+template <typename T> using C2 = typename c2t<T>::type;
+
+template <typename T>
+__device__ __forceinline__ C2<T> mk(T x, T y) { C2<T> r; r.x = x; r.y = y; return r; }
+template <typename T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) {
+  return mk<T>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ C2<T> conjc(C2<T> a) { return mk<T>(a.x, -a.y); }
+// a * (S * i), S = +1 or -1
+template <typename T, int S>
+__device__ __forceinline__ C2<T> mul_si(C2<T> a) {
+  return S > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers, natural order in and out, sign S of the exponent.
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__device__ __forceinline__ void dft2(C2<T>* a) {
+  C2<T> t = a[0];
+  a[0] = cadd<T>(t, a[1]);
+  a[1] = csub<T>(t, a[1]);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft4(C2<T>& a0, C2<T>& a1, C2<T>& a2, C2<T>& a3) {
+  C2<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2);
+  C2<T> t2 = cadd<T>(a1, a3), t3 = mul_si<T, S>(csub<T>(a1, a3));
+  a0 = cadd<T>(t0, t2);
+  a2 = csub<T>(t0, t2);
+  a1 = cadd<T>(t1, t3);
+  a3 = csub<T>(t1, t3);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft4a(C2<T>* a) { dft4<T, S>(a[0], a[1], a[2], a[3]); }
+
+template <typename T, int S>
+__device__ __forceinline__ void dft8(C2<T>* a) {
+  // even / odd halves, then w8^k combine
+  C2<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  C2<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<T, S>(e0, e1, e2, e3);
+  dft4<T, S>(o0, o1, o2, o3);
+  const T h = (T)0.70710678118654752440;
+  // w^1 = h(1 + S i), w^2 = S i, w^3 = h(-1 + S i)
+  C2<T> w1o = mk<T>(h * (o1.x - S * o1.y), h * (o1.y + S * o1.x));
+  C2<T> w2o = mul_si<T, S>(o2);
+  C2<T> w3o = mk<T>(h * (-o3.x - S * o3.y), h * (-o3.y + S * o3.x));
+  a[0] = cadd<T>(e0, o0); a[4] = csub<T>(e0, o0);
+  a[1] = cadd<T>(e1, w1o); a[5] = csub<T>(e1, w1o);
+  a[2] = cadd<T>(e2, w2o); a[6] = csub<T>(e2, w2o);
+  a[3] = cadd<T>(e3, w3o); a[7] = csub<T>(e3, w3o);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft16(C2<T>* a) {
+  C2<T> e[8], o[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { e[i] = a[2 * i]; o[i] = a[2 * i + 1]; }
+  dft8<T, S>(e);
+  dft8<T, S>(o);
+  const T c1 = (T)0.92387953251128675613;  // cos(pi/8)
+  const T s1 = (T)0.38268343236508977173;  // sin(pi/8)
+  const T h = (T)0.70710678118654752440;
+  // w16^k = (cos(k pi/8), S sin(k pi/8))
+  const T wr[8] = {(T)1, c1, h, s1, (T)0, -s1, -h, -c1};
+  const T wi[8] = {(T)0, s1, h, c1, (T)1, c1, h, s1};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    C2<T> w = mk<T>(wr[k], (T)S * wi[k]);
+    C2<T> t = (k == 0) ? o[k] : (k == 4 ? mul_si<T, S>(o[k]) : cmul<T>(w, o[k]));
+    a[k] = cadd<T>(e[k], t);
+    a[k + 8] = csub<T>(e[k], t);
+  }
+}
+
+template <typename T, int S, int RADIX>
+__device__ __forceinline__ void dft_r(C2<T>* a) {
+  if constexpr (RADIX == 2) dft2<T, S>(a);
+  else if constexpr (RADIX == 4) dft4a<T, S>(a);
+  else if constexpr (RADIX == 8) dft8<T, S>(a);
+  else if constexpr (RADIX == 16) dft16<T, S>(a);
+}
+
+// padded LDS index: one spare element after every 16 (bank spreading)
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_elems(int n) { return n + n / 16; }
+
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TEAM <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// One Stockham stage with Ns = NS, then recurse into the next.
+template <typename T, int N, int TEAM, int DIR, int NS>
+__device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
+                                          const C2<T>* tw, int lane) {
+  constexpr int R = N / TEAM;
+  constexpr int REM = N / NS;
+  constexpr int RAD = cmin(16, cmin(R, REM));
+  constexpr bool LAST = (NS * RAD == N);
+  constexpr int BPL = R / RAD;
+  constexpr int TSTRIDE = N / (NS * RAD);
+#pragma unroll
+  for (int t = 0; t < BPL; ++t) {
+    const int j = lane + TEAM * t;
+    const int k = j & (NS - 1);
+    C2<T> x[RAD];
+#pragma unroll
+    for (int m = 0; m < RAD; ++m) x[m] = v[t + m * BPL];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int m = 1; m < RAD; ++m) {
+        C2<T> w = tw[m * k * TSTRIDE];
+        if constexpr (DIR < 0) w.y = -w.y;
+        x[m] = cmul<T>(x[m], w);
+      }
+    }
+    dft_r<T, DIR, RAD>(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int m = 0; m < RAD; ++m) v[t + m * BPL] = x[m];
+    } else {
+      const int base = (j - k) * RAD + k;
+#pragma unroll
+      for (int m = 0; m < RAD; ++m) lds[lpad(base + m * NS)] = x[m];
+    }
+  }
+  if constexpr (!LAST) {
+    team_sync<TEAM>();
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = lds[lpad(lane + TEAM * q)];
+    team_sync<TEAM>();
+    fft_stage<T, N, TEAM, DIR, NS * RAD>(v, lds, tw, lane);
+  }
+}
+
+// In-place unnormalised DFT of length N over a team: DIR = -1 forward
+// (exp(-2 pi i jk/N)), +1 inverse.  lds: lds_elems(N) elements private to
+// the team; tw: N-entry table exp(+2 pi i t/N) (global or LDS).
+template <typename T, int N, int TEAM, int DIR>
+__device__ __forceinline__ void team_fft(C2<T> (&v)[N / TEAM], C2<T>* lds,
+                                         const C2<T>* tw, int lane) {
+  static_assert(N % TEAM == 0 && N / TEAM >= 2, "team too large for N");
+  static_assert((N & (N - 1)) == 0, "power-of-two lengths only");
+  fft_stage<T, N, TEAM, DIR, 1>(v, lds, tw, lane);
+}
+
+}  // namespace cmif

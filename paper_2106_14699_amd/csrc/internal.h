@@ -1,0 +1,69 @@
+// Internal definitions shared by the kernels and the host scheduler of
+// libcmif.  Not part of the public ABI.
+//
+// HBM layouts (per image pair; complex<T> = float2 or double2):
+//   row spectra  X[label][tile][y][TW]      tile = k_x / TW, y in [0, H)
+//   2D spectra   F[label][c][k_y]           c in [0, P_w/2), k_y in [0, P_h)
+//   pair columns Z[a*Q_B+b][tile][i][TW]    i = map row in [0, S_h)
+// where TW = 64 B / sizeof(complex<T>) (8 for FP32, 4 for FP64), so one
+// (tile, row) record is one 64-byte segment.  Column c = 0 holds the two
+// real-input special frequencies packed as one complex value: the k_x = 0
+// and k_x = P_w/2 row values are real for real input, so slot 0 stores
+// X(y, 0) + i X(y, P_w/2); the column transform of that packed column yields
+// G0(k_y) + i G1(k_y) with both G0 and G1 Hermitian, which the pair kernel
+// separates again.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/cmif.h"
+
+namespace cmif {
+
+constexpr int kMaxBatch = 16;  // angles per pipeline pass (kernel argument)
+constexpr int kMinP = 128;
+constexpr int kMaxP = 2048;
+
+struct RotArgs {
+  int32_t c[kMaxBatch];  // round(cos(theta) * 2^16)
+  int32_t s[kMaxBatch];  // round(sin(theta) * 2^16)
+};
+
+// Argmax partial for one (angle, row block): best eligible MI and its flat
+// map index, -1 when the block had no eligible entry.
+struct ArgPartial {
+  double mi;
+  int64_t idx;
+  int64_t n;
+};
+
+template <typename T>
+constexpr int tile_width() { return 64 / (2 * (int)sizeof(T)); }
+
+// Lanes per FFT team: at most 8 points per lane (radix-8 stages), so a
+// 1024-point transform is spread over two waves and 2048 over four.
+constexpr int team_for(int p) { return p <= 512 ? 64 : p / 8; }
+
+// Team size of the column kernels, whose workgroup holds one team per column
+// of a TW-wide tile: capped so that TW teams fit in 1024 lanes.
+template <typename T>
+constexpr int col_team_for(int p) {
+  return team_for(p) * tile_width<T>() <= 1024 ? team_for(p)
+                                               : 1024 / tile_width<T>();
+}
+
+// Map row of a circular correlation row y (P_h periodic): chi_y = y for
+// y <= h_b - 1, chi_y = y - P_h for y >= P_h - h_a + 1; -1 if unused.
+__host__ __device__ inline int circ_to_map(int y, int p, int h_a, int h_b) {
+  if (y <= h_b - 1) return y + h_a - 1;
+  if (y >= p - h_a + 1) return y - p + h_a - 1;
+  return -1;
+}
+
+// Inverse of circ_to_map: circular index of map row i.
+__host__ __device__ inline int map_to_circ(int i, int p, int h_a) {
+  int chi = i - (h_a - 1);
+  return chi >= 0 ? chi : chi + p;
+}
+
+}  // namespace cmif

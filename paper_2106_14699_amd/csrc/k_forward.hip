@@ -1,0 +1,219 @@
+// Forward 2D real-to-complex transforms of the masked level-set indicators
+// (Sec. 3.1, Eq. 8) of A (once) and of the rotated B (per angle).
+//
+// k_fwd_rows: one workgroup per image row (and angle).  Each lane resamples
+//   its pixels of the row by the fixed-point nearest-neighbour rotation
+//   (Sec. 3.6), then every team transforms two level sets at once: the
+//   complex input L_a + i L_{a+1} (zero-padded to P_w) goes through one
+//   forward FFT and the two real spectra are separated with the Hermitian
+//   mirror X(P - k).  Output: X[label][tile][y][TW], k_x in [0, P_w/2) with
+//   the k_x = 0 and k_x = P_w/2 values packed in slot 0.
+// k_fwd_cols: one workgroup per (tile of TW columns, label, angle); the tile
+//   (H rows x 64 B) is read coalesced into LDS, each team transforms one
+//   column along y (zero-padded to P_h) and writes it contiguously as
+//   F[label][c][k_y].
+#include "fft_core.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace cmif {
+
+__device__ __forceinline__ int floordiv_pos_pow2(long long a, int shift) {
+  // floor(a / 2^shift) for any sign (arithmetic shift)
+  return (int)(a >> shift);
+}
+
+template <typename T, int P, int TEAM>
+__global__ void __launch_bounds__(4 * TEAM)
+k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
+           int H, int W, int Q, RotArgs rot, C2<T>* __restrict__ xrow,
+           long long angle_stride, const C2<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  const int y = blockIdx.x;
+  const int beta = blockIdx.y;
+  const int nteams = blockDim.x / TEAM;
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  C2<T>* lds = smem + team * lds_elems(P);
+
+  const long long c = rot.c[beta], s = rot.s[beta];
+  const long long one = 65536;
+  uint8_t lv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int x = lane + TEAM * q;
+    uint8_t l = 255;
+    if (x < W) {
+      const long long X = 2LL * x - (W - 1);
+      const long long Y = 2LL * y - (H - 1);
+      const long long xs2 = c * X - s * Y;
+      const long long ys2 = s * X + c * Y;
+      const int xs = floordiv_pos_pow2(xs2 + (long long)(W - 1) * one + one, 17);
+      const int ys = floordiv_pos_pow2(ys2 + (long long)(H - 1) * one + one, 17);
+      if (xs >= 0 && xs < W && ys >= 0 && ys < H) {
+        const int src = ys * W + xs;
+        if (msk == nullptr || msk[src]) {
+          const uint8_t v = lab[src];
+          if (v < Q) l = v;
+        }
+      }
+    }
+    lv[q] = l;
+  }
+
+  const int npacks = (Q + 1) / 2;
+  const int iters = (npacks + nteams - 1) / nteams;
+  const long long plane = (long long)(P / 2) * H;  // elements per label
+  C2<T>* out = xrow + beta * angle_stride;
+  for (int it = 0; it < iters; ++it) {
+    const int pk = team + it * nteams;
+    const bool active = pk < npacks;
+    const int a0 = 2 * pk, a1 = 2 * pk + 1;
+    C2<T> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      v[q] = mk<T>(lv[q] == a0 ? (T)1 : (T)0, lv[q] == a1 ? (T)1 : (T)0);
+    team_fft<T, P, TEAM, -1>(v, lds, tw, lane);
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[lpad(lane + TEAM * q)] = v[q];
+    team_sync<TEAM>();
+    C2<T> vm[R / 2];
+#pragma unroll
+    for (int q = 0; q < R / 2; ++q) {
+      const int k = lane + TEAM * q;
+      vm[q] = lds[lpad((P - k) & (P - 1))];
+    }
+    team_sync<TEAM>();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < R / 2; ++q) {
+        const int k = lane + TEAM * q;
+        C2<T> f0, f1;
+        if (k == 0) {
+          // X(0) and X(P/2) of each real sequence are real: pack them
+          f0 = mk<T>(v[0].x, v[R / 2].x);
+          f1 = mk<T>(v[0].y, v[R / 2].y);
+        } else {
+          f0 = mk<T>((v[q].x + vm[q].x) * (T)0.5, (v[q].y - vm[q].y) * (T)0.5);
+          f1 = mk<T>((v[q].y + vm[q].y) * (T)0.5, (vm[q].x - v[q].x) * (T)0.5);
+        }
+        const long long o = ((long long)(k / TW) * H + y) * TW + (k % TW);
+        out[(long long)a0 * plane + o] = f0;
+        if (a1 < Q) out[(long long)a1 * plane + o] = f1;
+      }
+    }
+  }
+}
+
+template <typename T, int P, int TEAM>
+__global__ void __launch_bounds__(tile_width<T>() * TEAM)
+k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
+           long long x_label_stride, C2<T>* __restrict__ F,
+           long long f_angle_stride, long long f_label_stride,
+           const C2<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  const int t = blockIdx.x, lbl = blockIdx.y, beta = blockIdx.z;
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const C2<T>* src = xrow + beta * x_angle_stride + lbl * x_label_stride +
+                     (long long)t * H * TW;
+  // coalesced tile load: H rows of one 64-byte segment each
+  {
+    const int n16 = H * TW * (int)sizeof(C2<T>) / 16;
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    float4* d4 = reinterpret_cast<float4*>(smem);
+    for (int i = threadIdx.x; i < n16; i += blockDim.x) d4[i] = s4[i];
+  }
+  __syncthreads();
+  C2<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int y = lane + TEAM * q;
+    v[q] = y < H ? smem[y * TW + team] : mk<T>((T)0, (T)0);
+  }
+  __syncthreads();
+  team_fft<T, P, TEAM, -1>(v, smem + team * lds_elems(P), tw, lane);
+  C2<T>* dst = F + beta * f_angle_stride + lbl * f_label_stride +
+               (long long)(t * TW + team) * P;
+#pragma unroll
+  for (int q = 0; q < R; ++q) dst[lane + TEAM * q] = v[q];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
+  constexpr int TEAM = team_for(P);
+  const int npacks = (a.Q + 1) / 2;
+  const size_t per_team = (size_t)lds_elems(P) * sizeof(C2<T>);
+  int nteams = npacks;
+  const int max_teams_lds = (int)(65536 / per_team) > 0 ? (int)(65536 / per_team) : 1;
+  if (nteams > max_teams_lds) nteams = max_teams_lds;
+  if (nteams > 4) nteams = 4;  // matches the kernel's launch bound
+  if (nteams < 1) nteams = 1;
+  const size_t shm = per_team * nteams;
+  auto fn = k_fwd_rows<T, P, TEAM>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shm);
+  if (e != hipSuccess) return e;
+  dim3 grid(a.H, a.nb);
+  hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.lab, a.msk, a.H,
+                     a.W, a.Q, a.rot, a.xrow, a.angle_stride, a.tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fwd_rows(int P, const FwdRowsArgs<T>& a, hipStream_t st) {
+  switch (P) {
+    case 128: return launch_rows_p<T, 128>(a, st);
+    case 256: return launch_rows_p<T, 256>(a, st);
+    case 512: return launch_rows_p<T, 512>(a, st);
+    case 1024: return launch_rows_p<T, 1024>(a, st);
+    case 2048: return launch_rows_p<T, 2048>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P>
+static hipError_t launch_cols_p(const FwdColsArgs<T>& a, hipStream_t st) {
+  constexpr int TEAM = col_team_for<T>(P);
+  constexpr int TW = tile_width<T>();
+  const size_t shm = (size_t)TW * lds_elems(P) * sizeof(C2<T>);
+  auto fn = k_fwd_cols<T, P, TEAM>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shm);
+  if (e != hipSuccess) return e;
+  dim3 grid(a.tiles, a.Q, a.nb);
+  hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.xrow, a.H,
+                     a.x_angle_stride, a.x_label_stride, a.F, a.f_angle_stride,
+                     a.f_label_stride, a.tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fwd_cols(int P, const FwdColsArgs<T>& a, hipStream_t st) {
+  switch (P) {
+    case 128: return launch_cols_p<T, 128>(a, st);
+    case 256: return launch_cols_p<T, 256>(a, st);
+    case 512: return launch_cols_p<T, 512>(a, st);
+    case 1024: return launch_cols_p<T, 1024>(a, st);
+    case 2048: return launch_cols_p<T, 2048>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_fwd_rows<float>(int, const FwdRowsArgs<float>&, hipStream_t);
+template hipError_t launch_fwd_rows<double>(int, const FwdRowsArgs<double>&, hipStream_t);
+template hipError_t launch_fwd_cols<float>(int, const FwdColsArgs<float>&, hipStream_t);
+template hipError_t launch_fwd_cols<double>(int, const FwdColsArgs<double>&, hipStream_t);
+
+}  // namespace cmif

@@ -1,0 +1,204 @@
+// Small kernels: twiddle / log tables, fills, label-range check, and the
+// Alg. 1 argmax (per angle over eligible displacements, then across angles).
+#include "entropy.h"
+#include "fft_core.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace cmif {
+
+// tw[t] = exp(+2 pi i t / P) evaluated in FP64 with sincospi (exact argument
+// reduction of t/P), stored in FP32 and FP64; logtab[j] = log2(1 + j/256),
+// logtab[256 + j] = 1 / (1 + j/256).
+__global__ void k_init_tables(float2* tw32, double2* tw64, int P, double* logtab) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < P) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)P, &s, &c);
+    if (tw64) tw64[t] = make_double2(c, s);
+    if (tw32) tw32[t] = make_float2((float)c, (float)s);
+  }
+  if (logtab && t < 256) {
+    const double m = 1.0 + (double)t / 256.0;
+    logtab[t] = log2(m);
+    logtab[256 + t] = 1.0 / m;
+  }
+}
+
+hipError_t launch_init_tables(void* tw32, void* tw64, int P, double* logtab,
+                              hipStream_t st) {
+  const int n = P > 256 ? P : 256;
+  hipLaunchKernelGGL(k_init_tables, dim3((n + 255) / 256), dim3(256), 0, st,
+                     (float2*)tw32, (double2*)tw64, P, logtab);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+// Counts pixels inside the mask whose label is >= Q (they belong to no
+// level set; the direct method would have no histogram bin for them).
+__global__ void k_check_labels(const uint8_t* lab, const uint8_t* msk,
+                               long long n, int Q, cmif_stats* stats) {
+  uint32_t bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    if ((msk == nullptr || msk[i]) && lab[i] >= Q) ++bad;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+  if ((threadIdx.x % 64) == 0 && bad) atomicAdd(&stats->label_errors, bad);
+}
+
+hipError_t launch_check_labels(const uint8_t* lab, const uint8_t* msk,
+                               long long n, int Q, cmif_stats* stats,
+                               hipStream_t st) {
+  if (stats == nullptr || n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_check_labels, dim3((unsigned)blocks), dim3(256), 0, st,
+                     lab, msk, n, Q, stats);
+  return hipGetLastError();
+}
+
+// (mi, idx) ordering of Alg. 1 inside one transform: larger MI wins, equal
+// MI goes to the smaller row-major index; idx < 0 means "none".
+__device__ __forceinline__ bool better(double m1, long long i1, double m2,
+                                       long long i2) {
+  if (i2 < 0) return i1 >= 0;
+  if (i1 < 0) return false;
+  return m1 > m2 || (m1 == m2 && i1 < i2);
+}
+
+// Per (row chunk, angle): best eligible entry, N >= gamma * max N compared
+// in FP64.
+__global__ void __launch_bounds__(256)
+k_argmax_partial(const double* __restrict__ mi, const int32_t* __restrict__ nmap,
+                 long long angle_stride, const uint32_t* __restrict__ maxn,
+                 int sh, int sw, int rows_per_chunk, int nchunks, double gamma,
+                 ArgPartial* __restrict__ partial) {
+  const int chunk = blockIdx.x, beta = blockIdx.y;
+  const double thr = gamma * (double)maxn[beta];
+  const int r0 = chunk * rows_per_chunk;
+  const int r1 = min(sh, r0 + rows_per_chunk);
+  const long long lo = (long long)r0 * sw, hi = (long long)r1 * sw;
+  const double* m = mi + beta * angle_stride;
+  const int32_t* nn = nmap + beta * angle_stride;
+  double bm = 0.0;
+  long long bi = -1;
+  int bn = 0;
+  for (long long k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    const int n = nn[k];
+    if ((double)n >= thr) {
+      const double v = m[k];
+      if (better(v, k, bm, bi)) { bm = v; bi = k; bn = n; }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double om = __shfl_xor(bm, o, 64);
+    const long long oi = __shfl_xor(bi, o, 64);
+    const int on = __shfl_xor(bn, o, 64);
+    if (better(om, oi, bm, bi)) { bm = om; bi = oi; bn = on; }
+  }
+  __shared__ double sm[4];
+  __shared__ long long si[4];
+  __shared__ int sn[4];
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x % 64) == 0) { sm[w] = bm; si[w] = bi; sn[w] = bn; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x / 64); ++k)
+      if (better(sm[k], si[k], bm, bi)) { bm = sm[k]; bi = si[k]; bn = sn[k]; }
+    ArgPartial p;
+    p.mi = bm;
+    p.idx = bi;
+    p.n = bn;
+    partial[beta * nchunks + chunk] = p;
+  }
+}
+
+hipError_t launch_argmax(const ArgmaxArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_argmax_partial, dim3(a.nchunks, a.nb), dim3(256), 0, st,
+                     a.mi, a.n, a.angle_stride, a.maxn, a.sh, a.sw,
+                     a.rows_per_chunk, a.nchunks, a.gamma, a.partial);
+  return hipGetLastError();
+}
+
+// One thread: per angle of the batch reduce the chunk partials, then fold
+// the angles in order into the running best.  As in Alg. 1 the best starts
+// as the identity with I = 0 (angle_index -1, chi = 0) and only a strictly
+// larger MI replaces it, so the earliest angle wins ties.
+struct AngleVals {
+  double v[kMaxBatch];
+};
+
+__global__ void k_argmax_final(const ArgPartial* __restrict__ partial, int nb,
+                               int nchunks, int sw, int ha, int wa, int angle0,
+                               AngleVals angles,
+                               cmif_best* __restrict__ per_angle,
+                               cmif_best* __restrict__ running, int first_batch,
+                               cmif_best* __restrict__ best_out,
+                               int last_batch) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  cmif_best run = *running;
+  if (first_batch) {
+    run.angle_index = -1;
+    run.dy = 0;
+    run.dx = 0;
+    run.reserved = 0;
+    run.angle_rad = 0.0;
+    run.mi = 0.0;
+    run.n = 0;
+  }
+  for (int b = 0; b < nb; ++b) {
+    double bm = 0.0;
+    long long bi = -1;
+    long long bn = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      const ArgPartial p = partial[b * nchunks + c];
+      if (better(p.mi, p.idx, bm, bi)) { bm = p.mi; bi = p.idx; bn = p.n; }
+    }
+    cmif_best r;
+    r.angle_index = angle0 + b;
+    r.angle_rad = angles.v[b];
+    r.reserved = 0;
+    if (bi >= 0) {
+      r.dy = (int)(bi / sw) - (ha - 1);
+      r.dx = (int)(bi % sw) - (wa - 1);
+      r.mi = bm;
+      r.n = bn;
+    } else {
+      r.dy = 0;
+      r.dx = 0;
+      r.mi = 0.0;
+      r.n = 0;
+    }
+    if (per_angle) per_angle[angle0 + b] = r;
+    if (r.mi > run.mi) run = r;  // I starts at 0 with the identity
+  }
+  *running = run;
+  if (last_batch && best_out) *best_out = run;
+}
+
+hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st) {
+  AngleVals av;
+  for (int b = 0; b < kMaxBatch; ++b) av.v[b] = a.angles[b];
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, st, a.partial, a.nb,
+                     a.nchunks, a.sw, a.ha, a.wa, a.angle0, av,
+                     a.per_angle, a.running, a.first_batch, a.best_out,
+                     a.last_batch);
+  return hipGetLastError();
+}
+
+}  // namespace cmif

@@ -1,0 +1,120 @@
+// Pair column pass: conjugate spectral products and the inverse transform
+// along y for every label pair (Sec. 3.2, Eq. 9; Eq. 7 in the frequency
+// domain: sum_x f(x) g(x + k) has spectrum conj(F) G).
+//
+// One workgroup per (tile of TW spectrum columns, label a of A, angle); each
+// team owns one column c and keeps conj(F_A,a(:, c)) in registers while it
+// loops over all labels b of B: product, inverse FFT along y (length P_h),
+// then the TW columns are transposed through LDS so that every map row i of
+// the tile leaves as one 64-byte segment of Z[a*Q_B+b][tile][i][TW].  Rows
+// of the circular correlation that map to no displacement are not stored.
+#include "fft_core.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace cmif {
+
+// Separate the packed column 0: W = G0 + i G1 with G0, G1 Hermitian in k.
+template <typename T>
+__device__ __forceinline__ void unpack0(C2<T> w, C2<T> wm, C2<T>& g0, C2<T>& g1) {
+  // g0 = (w + conj(wm)) / 2,  g1 = (w - conj(wm)) / (2i)
+  g0 = mk<T>((w.x + wm.x) * (T)0.5, (w.y - wm.y) * (T)0.5);
+  g1 = mk<T>((w.y + wm.y) * (T)0.5, (wm.x - w.x) * (T)0.5);
+}
+
+template <typename T, int P, int TEAM>
+__global__ void __launch_bounds__(tile_width<T>() * TEAM)
+k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
+            const C2<T>* __restrict__ FB, long long fb_angle_stride,
+            long long fb_label_stride, int QB, int ha, int hb, int sh,
+            C2<T>* __restrict__ Z, long long z_angle_stride,
+            long long z_pair_stride, const C2<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  const int t = blockIdx.x, a = blockIdx.y, beta = blockIdx.z;
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int c = t * TW + team;
+  C2<T>* lds = smem + team * lds_elems(P);
+
+  const C2<T>* fa_col = FA + a * fa_label_stride + (long long)c * P;
+  C2<T> fa[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) fa[q] = fa_col[lane + TEAM * q];
+  const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
+  C2<T>* z_base = Z + beta * z_angle_stride + (long long)t * sh * TW;
+  const int n16 = sh * TW * (int)sizeof(C2<T>) / 16;
+
+  for (int b = 0; b < QB; ++b) {
+    const C2<T>* fb_col = fb_base + b * fb_label_stride;
+    C2<T> v[R];
+    if (c != 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = cmulc<T>(fa[q], fb_col[lane + TEAM * q]);
+    } else {
+      // slot 0 packs the k_x = 0 and k_x = P_w/2 columns (both Hermitian);
+      // the mirrored values are re-read so no extra registers stay live
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int k = lane + TEAM * q;
+        const int km = (P - k) & (P - 1);
+        C2<T> ga0, ga1, gb0, gb1;
+        unpack0<T>(fa[q], fa_col[km], ga0, ga1);
+        unpack0<T>(fb_col[k], fb_col[km], gb0, gb1);
+        const C2<T> y0 = cmulc<T>(ga0, gb0);     // Hermitian in k
+        const C2<T> y1 = cmulc<T>(ga1, gb1);     // Hermitian in k
+        v[q] = mk<T>(y0.x - y1.y, y0.y + y1.x);  // y0 + i y1
+      }
+    }
+    team_fft<T, P, TEAM, +1>(v, lds, tw, lane);
+    __syncthreads();  // every team is done with its exchange buffer
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = circ_to_map(lane + TEAM * q, P, ha, hb);
+      if (i >= 0) smem[i * TW + team] = v[q];
+    }
+    __syncthreads();
+    {
+      const float4* s4 = reinterpret_cast<const float4*>(smem);
+      float4* d4 = reinterpret_cast<float4*>(z_base + (long long)(a * QB + b) * z_pair_stride);
+      for (int i = threadIdx.x; i < n16; i += blockDim.x) d4[i] = s4[i];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int P>
+static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
+  constexpr int TEAM = col_team_for<T>(P);
+  constexpr int TW = tile_width<T>();
+  const size_t shm = (size_t)TW * lds_elems(P) * sizeof(C2<T>);
+  auto fn = k_pair_cols<T, P, TEAM>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shm);
+  if (e != hipSuccess) return e;
+  dim3 grid(a.tiles, a.QA, a.nb);
+  hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.FA, a.fa_label_stride,
+                     a.FB, a.fb_angle_stride, a.fb_label_stride, a.QB, a.ha,
+                     a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pair_cols(int P, const PairColsArgs<T>& a, hipStream_t st) {
+  switch (P) {
+    case 128: return launch_pc_p<T, 128>(a, st);
+    case 256: return launch_pc_p<T, 256>(a, st);
+    case 512: return launch_pc_p<T, 512>(a, st);
+    case 1024: return launch_pc_p<T, 1024>(a, st);
+    case 2048: return launch_pc_p<T, 2048>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_pair_cols<float>(int, const PairColsArgs<float>&, hipStream_t);
+template hipError_t launch_pair_cols<double>(int, const PairColsArgs<double>&, hipStream_t);
+
+}  // namespace cmif

@@ -1,0 +1,380 @@
+// Pair row pass with the fused entropy reduction (Sec. 3.2, Eq. 9-12), and
+// the count-emission variant of the same row pass.
+//
+// k_pair_rows: one workgroup owns one map row i (displacement chi_y) of one
+// angle and walks ALL label pairs for it, so the per-displacement histogram
+// state never leaves the chip:
+//   * teams split the labels of B: team g handles b in [g*BPW, (g+1)*BPW);
+//   * two pairs (a, b0), (a, b1) share one complex inverse FFT along x:
+//     W = Z_ab0 + i Z_ab1 (Hermitian extension of each half spectrum), so
+//     the real part is C_ab0 and the imaginary part C_ab1 on the circular
+//     x axis;
+//   * counts = rint(value / (P_h P_w)); |value - count| >= 0.25 at a used
+//     displacement flags the pair for the FP64 re-run; negatives clamp to 0;
+//   * per displacement and lane: C_b for the team's labels (exact uint32)
+//     and S_AB accumulated in FP64; the joint counts are also added into an
+//     LDS C_a accumulator (integer atomics, exact and order-free);
+//   * after each a, C_a is folded into S_A and N per displacement;
+//   * at the end S_B is subtracted per team, the team partials are summed in
+//     a fixed order, and MI = log2 N + (S_AB - S_A - S_B) / N is written.
+// k_pair_counts: the same row transforms, writing the rounded joint counts
+// and/or their order-free digests instead of entropies.
+#include "entropy.h"
+#include "fft_core.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace cmif {
+
+template <typename T>
+__device__ __forceinline__ T round_half_even(T v);
+template <>
+__device__ __forceinline__ float round_half_even<float>(float v) { return rintf(v); }
+template <>
+__device__ __forceinline__ double round_half_even<double>(double v) { return rint(v); }
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Loads row i of pairs p0 (and p1 when has1) and builds the packed complex
+// sequence W(k) = Z_p0(k) + i Z_p1(k), k = lane + TEAM*q, from the two half
+// spectra (slot 0 carries k = 0 and k = P/2, both real).
+template <typename T, int P, int TEAM>
+__device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
+                                          const C2<T>* __restrict__ z1,
+                                          bool has1, int tile_stride, int lane,
+                                          C2<T> (&w)[P / TEAM]) {
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  constexpr int HALF = P / 2;
+  C2<T> u0[R], u1[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+    const int kk = k > HALF ? P - k : k;
+    const int e = kk == HALF ? 0 : kk;
+    const int off = (e / TW) * tile_stride + (e % TW);
+    u0[q] = z0[off];
+    u1[q] = has1 ? z1[off] : mk<T>((T)0, (T)0);
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+    const int kk = k > HALF ? P - k : k;
+    if (kk == 0)
+      w[q] = mk<T>(u0[q].x, u1[q].x);
+    else if (kk == HALF)
+      w[q] = mk<T>(u0[q].y, u1[q].y);
+    else if (k < HALF)
+      w[q] = mk<T>(u0[q].x - u1[q].y, u0[q].y + u1[q].x);  // u0 + i u1
+    else
+      w[q] = mk<T>(u0[q].x + u1[q].y, u1[q].x - u0[q].y);  // conj(u0) + i conj(u1)
+  }
+}
+
+template <typename T, int P, int TEAM, int BPW, int NTMAX>
+__global__ void __launch_bounds__(NTMAX)
+k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
+            long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
+            int sw, int ph, const C2<T>* __restrict__ tw,
+            const double* __restrict__ logtab_g, double* __restrict__ mi_out,
+            long long mi_angle_stride, int32_t* __restrict__ n_out,
+            long long n_angle_stride, uint32_t* __restrict__ maxn,
+            uint32_t* __restrict__ flags, cmif_stats* __restrict__ stats) {
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nteams = blockDim.x / TEAM;
+  const int NT = blockDim.x;
+  C2<T>* exch = reinterpret_cast<C2<T>*>(smem_raw);
+  double* ltab = reinterpret_cast<double*>(exch + (size_t)nteams * lds_elems(P));
+  double* sa_l = ltab + 512;                              // S_A per x
+  uint32_t* n_l = reinterpret_cast<uint32_t*>(sa_l + P);  // N per x
+  uint32_t* slot = n_l + P;                               // [2][P] C_a
+
+  const int i = blockIdx.x;     // map row
+  const int beta = blockIdx.y;  // angle within batch
+  const int tid = threadIdx.x;
+  const int team = tid / TEAM;
+  const int lane = tid % TEAM;
+  C2<T>* lds = exch + team * lds_elems(P);
+
+  for (int x = tid; x < 512; x += NT) ltab[x] = logtab_g[x];
+  for (int x = tid; x < 2 * P; x += NT) slot[x] = 0u;
+  for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
+
+  const T scale = (T)1 / ((T)ph * (T)P);
+  const C2<T>* zrow = Z + beta * z_angle_stride + (long long)i * TW;
+  const int tile_stride = sh * TW;
+
+  uint32_t cb[BPW][R];
+  double sab[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    sab[q] = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < BPW; ++bb) cb[bb][q] = 0u;
+  }
+  float maxres = 0.0f;
+  __syncthreads();
+
+  const int b_first = team * BPW;
+  const int nq = QA * QB;
+  for (int a = 0; a < QA; ++a) {
+    uint32_t* sl = slot + (a & 1) * P;
+#pragma unroll
+    for (int pk = 0; pk < BPW / 2; ++pk) {
+      const int b0 = b_first + 2 * pk, b1 = b0 + 1;
+      const bool has0 = b0 < QB, has1 = b1 < QB;
+      C2<T> w[R];
+      if (has0) {
+        load_pack<T, P, TEAM>(zrow + (long long)(a * QB + b0) * z_pair_stride,
+                              zrow + (long long)(a * QB + b1) * z_pair_stride,
+                              has1, tile_stride, lane, w);
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
+      }
+      team_fft<T, P, TEAM, +1>(w, lds, tw, lane);
+
+      bool bad0 = false, bad1 = false;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int x = lane + TEAM * q;
+        if (has0 && circ_to_map(x, P, wa, wb) >= 0) {
+          const T v0 = w[q].x * scale, v1 = w[q].y * scale;
+          const T r0 = round_half_even<T>(v0), r1 = round_half_even<T>(v1);
+          const float e0 = (float)fabs(v0 - r0), e1 = (float)fabs(v1 - r1);
+          bad0 |= e0 >= 0.25f;
+          bad1 |= e1 >= 0.25f;
+          maxres = fmaxf(maxres, fmaxf(e0, has1 ? e1 : 0.0f));
+          const uint32_t n0 = r0 > (T)0 ? (uint32_t)r0 : 0u;
+          const uint32_t n1 = r1 > (T)0 ? (uint32_t)r1 : 0u;
+          cb[2 * pk][q] += n0;
+          cb[2 * pk + 1][q] += n1;
+          sab[q] += xlog2x_u32(n0, ltab) + xlog2x_u32(n1, ltab);
+          if (n0 + n1 != 0u) atomicAdd(&sl[x], n0 + n1);
+        }
+      }
+      if (__ballot(bad0 && has0) != 0ull && (tid % 64) == 0) {
+        const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b0], 1u);
+        if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+      }
+      if (__ballot(bad1 && has1) != 0ull && (tid % 64) == 0) {
+        const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b1], 1u);
+        if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+      }
+    }
+    // C_a of this a is complete in LDS: fold it into S_A and N
+    __syncthreads();
+    for (int x = tid; x < P; x += NT) {
+      const uint32_t cv = sl[x];
+      if (cv != 0u) {
+        sl[x] = 0u;
+        sa_l[x] += xlog2x_u32(cv, ltab);
+        n_l[x] += cv;
+      }
+    }
+  }
+
+  // S_AB - S_B per team, then a fixed-order sum over teams
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    double sb = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < BPW; ++bb) sb += xlog2x_u32(cb[bb][q], ltab);
+    sab[q] -= sb;
+  }
+  __syncthreads();
+  double* part = reinterpret_cast<double*>(lds);
+#pragma unroll
+  for (int q = 0; q < R; ++q) part[lane + TEAM * q] = sab[q];
+  __syncthreads();
+
+  uint32_t nmax = 0u;
+  for (int x = tid; x < P; x += NT) {
+    const int j = circ_to_map(x, P, wa, wb);
+    if (j >= 0) {
+      double tsum = 0.0;
+      for (int g = 0; g < nteams; ++g)
+        tsum += reinterpret_cast<const double*>(exch + g * lds_elems(P))[x];
+      const uint32_t nn = n_l[x];
+      double mi = 0.0;
+      if (nn > 0u) mi = log2_u32(nn, ltab) + (tsum - sa_l[x]) / (double)nn;
+      if (mi_out) mi_out[beta * mi_angle_stride + (long long)i * sw + j] = mi;
+      if (n_out) n_out[beta * n_angle_stride + (long long)i * sw + j] = (int32_t)nn;
+      nmax = nn > nmax ? nn : nmax;
+    }
+  }
+  // wave max of N and of the residual, one atomic per wave
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t on = __shfl_xor(nmax, o, 64);
+    nmax = on > nmax ? on : nmax;
+    maxres = fmaxf(maxres, __shfl_xor(maxres, o, 64));
+  }
+  if ((tid % 64) == 0) {
+    atomicMax(&maxn[beta], nmax);
+    if (stats)
+      atomicMax(reinterpret_cast<unsigned int*>(&stats->max_residual),
+                __float_as_uint(maxres));
+  }
+}
+
+// Count emission: workgroup (map row, angle); each team takes label pairs
+// two at a time (a-major order) and writes rint(count) to
+// counts[beta][pair][i][j] and/or adds sum_j count * splitmix64(i*S_w + j)
+// into digest[beta][pair] (64-bit wrap-around, order-free).
+template <typename T, int P, int TEAM>
+__global__ void __launch_bounds__(4 * TEAM)
+k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
+              long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
+              int sw, int ph, const C2<T>* __restrict__ tw,
+              int32_t* __restrict__ counts, long long counts_angle_stride,
+              uint64_t* __restrict__ digest) {
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T>* exch = reinterpret_cast<C2<T>*>(smem_raw);
+  const int nteams = blockDim.x / TEAM;
+  const int i = blockIdx.x, beta = blockIdx.y;
+  const int tid = threadIdx.x, team = tid / TEAM, lane = tid % TEAM;
+  C2<T>* lds = exch + team * lds_elems(P);
+  const T scale = (T)1 / ((T)ph * (T)P);
+  const C2<T>* zrow = Z + beta * z_angle_stride + (long long)i * TW;
+  const int nq = QA * QB;
+  const int npk = (nq + 1) / 2;
+  const int iters = (npk + nteams - 1) / nteams;
+  for (int it = 0; it < iters; ++it) {
+    const int pk = team + it * nteams;
+    const int p0 = 2 * pk, p1 = p0 + 1;
+    const bool has0 = p0 < nq, has1 = p1 < nq;
+    C2<T> w[R];
+    if (has0) {
+      load_pack<T, P, TEAM>(zrow + (long long)p0 * z_pair_stride,
+                            zrow + (long long)p1 * z_pair_stride, has1,
+                            sh * TW, lane, w);
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
+    }
+    team_fft<T, P, TEAM, +1>(w, lds, tw, lane);
+    uint64_t d0 = 0, d1 = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int j = circ_to_map(lane + TEAM * q, P, wa, wb);
+      if (has0 && j >= 0) {
+        const T r0 = round_half_even<T>(w[q].x * scale);
+        const T r1 = round_half_even<T>(w[q].y * scale);
+        const uint32_t n0 = r0 > (T)0 ? (uint32_t)r0 : 0u;
+        const uint32_t n1 = r1 > (T)0 ? (uint32_t)r1 : 0u;
+        const long long o = (long long)i * sw + j;
+        if (counts) {
+          int32_t* cbase = counts + beta * counts_angle_stride;
+          cbase[(long long)p0 * sh * sw + o] = (int32_t)n0;
+          if (has1) cbase[(long long)p1 * sh * sw + o] = (int32_t)n1;
+        }
+        const uint64_t wgt = splitmix64((uint64_t)o);
+        d0 += (uint64_t)n0 * wgt;
+        d1 += (uint64_t)n1 * wgt;
+      }
+    }
+    if (digest) {
+      d0 = wave_sum_u64(d0);
+      d1 = wave_sum_u64(d1);
+      if ((tid % 64) == 0 && has0) {
+        atomicAdd((unsigned long long*)&digest[beta * nq + p0], (unsigned long long)d0);
+        if (has1)
+          atomicAdd((unsigned long long*)&digest[beta * nq + p1], (unsigned long long)d1);
+      }
+    }
+  }
+}
+
+template <typename T, int P, int BPW, int NTMAX>
+static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm,
+                                hipStream_t st) {
+  constexpr int TEAM = team_for(P);
+  auto fn = k_pair_rows<T, P, TEAM, BPW, NTMAX>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shm);
+  if (e != hipSuccess) return e;
+  dim3 grid(a.sh, a.nb);
+  hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
+                     a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
+                     a.sh, a.sw, a.ph, a.tw, a.logtab, a.mi, a.mi_angle_stride,
+                     a.n, a.n_angle_stride, a.maxn, a.flags, a.stats);
+  return hipGetLastError();
+}
+
+template <typename T, int P, int BPW>
+static hipError_t launch_pr_bpw(const PairRowsArgs<T>& a, const PairRowsConfig& c,
+                                hipStream_t st) {
+  if (c.ntmax <= 256) return launch_pr_cfg<T, P, BPW, 256>(a, c.nteams, c.lds, st);
+  if (c.ntmax <= 512) return launch_pr_cfg<T, P, BPW, 512>(a, c.nteams, c.lds, st);
+  return launch_pr_cfg<T, P, BPW, 1024>(a, c.nteams, c.lds, st);
+}
+
+template <typename T, int P>
+static hipError_t launch_pr_p(const PairRowsArgs<T>& a, hipStream_t st) {
+  PairRowsConfig c;
+  if (!pair_rows_config(sizeof(T), P, a.QB, &c)) return hipErrorInvalidValue;
+  if (c.bpw == 4) return launch_pr_bpw<T, P, 4>(a, c, st);
+  if (c.bpw == 8) return launch_pr_bpw<T, P, 8>(a, c, st);
+  return launch_pr_bpw<T, P, 16>(a, c, st);
+}
+
+template <typename T>
+hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st) {
+  switch (P) {
+    case 128: return launch_pr_p<T, 128>(a, st);
+    case 256: return launch_pr_p<T, 256>(a, st);
+    case 512: return launch_pr_p<T, 512>(a, st);
+    case 1024: return launch_pr_p<T, 1024>(a, st);
+    case 2048: return launch_pr_p<T, 2048>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P>
+static hipError_t launch_pcnt_p(const PairCountsArgs<T>& a, hipStream_t st) {
+  constexpr int TEAM = team_for(P);
+  const size_t per_team = (size_t)lds_elems(P) * sizeof(C2<T>);
+  int nteams = 4;
+  while (nteams > 1 && per_team * nteams > 64 * 1024) --nteams;
+  const size_t shm = per_team * nteams;
+  auto fn = k_pair_counts<T, P, TEAM>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shm);
+  if (e != hipSuccess) return e;
+  dim3 grid(a.sh, a.nb);
+  hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
+                     a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
+                     a.sh, a.sw, a.ph, a.tw, a.counts, a.counts_angle_stride,
+                     a.digest);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st) {
+  switch (P) {
+    case 128: return launch_pcnt_p<T, 128>(a, st);
+    case 256: return launch_pcnt_p<T, 256>(a, st);
+    case 512: return launch_pcnt_p<T, 512>(a, st);
+    case 1024: return launch_pcnt_p<T, 1024>(a, st);
+    case 2048: return launch_pcnt_p<T, 2048>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_pair_rows<float>(int, const PairRowsArgs<float>&, hipStream_t);
+template hipError_t launch_pair_rows<double>(int, const PairRowsArgs<double>&, hipStream_t);
+template hipError_t launch_pair_counts<float>(int, const PairCountsArgs<float>&, hipStream_t);
+template hipError_t launch_pair_counts<double>(int, const PairCountsArgs<double>&, hipStream_t);
+
+}  // namespace cmif

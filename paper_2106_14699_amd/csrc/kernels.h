@@ -1,0 +1,145 @@
+// Launch interfaces of the libcmif kernels (host side).  Every launcher
+// enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.h"
+#include "internal.h"
+
+namespace cmif {
+
+template <typename T>
+struct FwdRowsArgs {
+  const uint8_t* lab;
+  const uint8_t* msk;  // nullable
+  int H, W, Q, nb;
+  RotArgs rot;
+  C2<T>* xrow;
+  long long angle_stride;
+  const C2<T>* tw;  // P_w-entry table
+};
+
+template <typename T>
+struct FwdColsArgs {
+  const C2<T>* xrow;
+  int H, tiles, Q, nb;
+  long long x_angle_stride, x_label_stride;
+  C2<T>* F;
+  long long f_angle_stride, f_label_stride;
+  const C2<T>* tw;  // P_h-entry table
+};
+
+template <typename T>
+struct PairColsArgs {
+  const C2<T>* FA;
+  long long fa_label_stride;
+  const C2<T>* FB;
+  long long fb_angle_stride, fb_label_stride;
+  int QA, QB, ha, hb, sh, tiles, nb;
+  C2<T>* Z;
+  long long z_angle_stride, z_pair_stride;
+  const C2<T>* tw;  // P_h-entry table
+};
+
+template <typename T>
+struct PairRowsArgs {
+  const C2<T>* Z;
+  long long z_angle_stride, z_pair_stride;
+  int QA, QB, ha, wa, hb, wb, sh, sw, ph, nb;
+  const C2<T>* tw;       // P_w-entry table
+  const double* logtab;  // 512 entries: log2(1 + j/256), 1/(1 + j/256)
+  double* mi;            // nullable, [nb][sh][sw]
+  long long mi_angle_stride;
+  int32_t* n;            // nullable, [nb][sh][sw]
+  long long n_angle_stride;
+  uint32_t* maxn;        // [nb]
+  uint32_t* flags;       // [nb][QA*QB]
+  cmif_stats* stats;     // nullable
+};
+
+template <typename T>
+struct PairCountsArgs {
+  const C2<T>* Z;
+  long long z_angle_stride, z_pair_stride;
+  int QA, QB, wa, wb, sh, sw, ph, nb;
+  const C2<T>* tw;       // P_w-entry table
+  int32_t* counts;       // nullable, [nb][QA*QB][sh][sw]
+  long long counts_angle_stride;
+  uint64_t* digest;      // nullable, [nb][QA*QB], accumulated (zero first)
+};
+
+struct ArgmaxArgs {
+  const double* mi;      // [nb][sh][sw]
+  const int32_t* n;      // [nb][sh][sw]
+  long long angle_stride;
+  const uint32_t* maxn;  // [nb]
+  int sh, sw, nb, rows_per_chunk, nchunks;
+  double gamma;
+  ArgPartial* partial;   // [nb][nchunks]
+};
+
+struct ArgmaxFinalArgs {
+  const ArgPartial* partial;
+  int nb, nchunks, sw, ha, wa;
+  int angle0;            // global index of the batch's first angle
+  double angles[kMaxBatch];  // angle values of the batch (radians)
+  cmif_best* per_angle;  // nullable, [n_angles] for this pair
+  cmif_best* running;    // running best over batches
+  int first_batch;
+  cmif_best* best_out;   // nullable: final copy target
+  int last_batch;
+};
+
+// Block shape of the pair row kernel: `bpw` labels of B per team, `nteams`
+// teams, the launch bound `ntmax` >= nteams * team_for(P), and its LDS bytes.
+struct PairRowsConfig {
+  int bpw, nteams, ntmax;
+  size_t lds;
+};
+
+inline size_t pair_rows_lds(size_t elem_real, int P, int nteams) {
+  return (size_t)nteams * lds_elems(P) * 2 * elem_real + 512 * sizeof(double) +
+         (size_t)P * sizeof(double) + 3 * (size_t)P * sizeof(uint32_t);
+}
+
+// false when no supported shape fits (LDS above 160 KiB or > 1024 lanes)
+inline bool pair_rows_config(size_t elem_real, int P, int QB, PairRowsConfig* c) {
+  const int team = team_for(P);
+  for (int bpw : {4, 8, 16}) {
+    const int nteams = (QB + bpw - 1) / bpw;
+    const int nt = nteams * team;
+    if (nt > 1024) continue;
+    const size_t lds = pair_rows_lds(elem_real, P, nteams);
+    if (lds > 160 * 1024) continue;
+    c->bpw = bpw;
+    c->nteams = nteams;
+    c->ntmax = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
+    c->lds = lds;
+    return true;
+  }
+  return false;
+}
+
+template <typename T>
+hipError_t launch_fwd_rows(int P, const FwdRowsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_fwd_cols(int P, const FwdColsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_pair_cols(int P, const PairColsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st);
+
+hipError_t launch_init_tables(void* tw32, void* tw64, int P, double* logtab,
+                              hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
+hipError_t launch_check_labels(const uint8_t* lab, const uint8_t* msk,
+                               long long n, int Q, cmif_stats* stats,
+                               hipStream_t st);
+hipError_t launch_argmax(const ArgmaxArgs& a, hipStream_t st);
+hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
+
+}  // namespace cmif

@@ -1,0 +1,197 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+the header declares, the ctypes mirrors match the C struct layouts, and the
+plan/argument validation rejects bad input before any device work.  None of
+these needs a GPU (cmif_plan is host-only)."""
+
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmif.h")
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import paper_2106_14699_amd as cm
+    return cm
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmif_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(cm):
+    names = header_functions()
+    assert set(names) == set(cm.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", cm.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    for n in names:
+        assert n in exported, n
+        assert hasattr(cm._lib, n)
+
+
+def test_struct_layouts_match_header(cm, tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "cmif.h"
+#define P(s, f) printf(#s "." #f " %zu\n", offsetof(s, f))
+int main(void) {
+  printf("desc %zu\n", sizeof(cmif_plan_desc));
+  printf("stats %zu\n", sizeof(cmif_stats));
+  printf("best %zu\n", sizeof(cmif_best));
+  printf("inputs %zu\n", sizeof(cmif_inputs));
+  printf("outputs %zu\n", sizeof(cmif_outputs));
+  P(cmif_plan_desc, gamma); P(cmif_plan_desc, angle_batch);
+  P(cmif_plan_desc, angles_rad); P(cmif_best, angle_rad); P(cmif_best, n);
+  P(cmif_stats, max_residual); P(cmif_outputs, stats);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog),
+                    "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run(
+        [str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+        if l)
+    assert int(got["desc"]) == ctypes.sizeof(cm.cmif_plan_desc)
+    assert int(got["stats"]) == ctypes.sizeof(cm.cmif_stats)
+    assert int(got["best"]) == ctypes.sizeof(cm.cmif_best)
+    assert int(got["inputs"]) == ctypes.sizeof(cm.cmif_inputs)
+    assert int(got["outputs"]) == ctypes.sizeof(cm.cmif_outputs)
+    assert int(got["cmif_plan_desc.gamma"]) == cm.cmif_plan_desc.gamma.offset
+    assert int(got["cmif_plan_desc.angle_batch"]) == cm.cmif_plan_desc.angle_batch.offset
+    assert int(got["cmif_plan_desc.angles_rad"]) == cm.cmif_plan_desc.angles_rad.offset
+    assert int(got["cmif_best.angle_rad"]) == cm.cmif_best.angle_rad.offset
+    assert int(got["cmif_best.n"]) == cm.cmif_best.n.offset
+    assert int(got["cmif_stats.max_residual"]) == cm.cmif_stats.max_residual.offset
+    assert int(got["cmif_outputs.stats"]) == cm.cmif_outputs.stats.offset
+
+
+def make_desc(cm, sizes=((64, 64, 64, 64),), qa=4, qb=4, angles=(0.0,),
+              gamma=0.5, precision=0, mode=0, flags=0):
+    n = len(sizes)
+    arrs = [(ctypes.c_int32 * n)(*[s[k] for s in sizes]) for k in range(4)]
+    ang = (ctypes.c_double * max(len(angles), 1))(*angles) if angles else None
+    d = cm.cmif_plan_desc()
+    d.n_pairs = n
+    d.h_a, d.w_a, d.h_b, d.w_b = [ctypes.cast(a, ctypes.POINTER(ctypes.c_int32))
+                                  for a in arrs]
+    d.q_a, d.q_b = qa, qb
+    d.n_angles = len(angles) if angles else 1
+    d.angles_rad = ctypes.cast(ang, ctypes.POINTER(ctypes.c_double)) if ang else None
+    d.gamma = gamma
+    d.precision, d.mode, d.flags = precision, mode, flags
+    d._keep = (arrs, ang)
+    return d
+
+
+def plan_status(cm, d):
+    h = ctypes.c_void_p()
+    s = cm._lib.cmif_plan(ctypes.byref(d), ctypes.byref(h))
+    if s == 0:
+        cm.cmif_plan_free(h.value)
+    return s
+
+
+@pytest.mark.parametrize("field,value,expect", [
+    ("q_a", 0, 1), ("q_a", 65, 1), ("q_b", 0, 1), ("gamma", -0.1, 1),
+    ("gamma", 1.5, 1), ("gamma", float("nan"), 1), ("precision", 7, 1),
+    ("mode", 3, 1), ("flags", 1 << 20, 1), ("n_pairs", 0, 1),
+    ("n_angles", 0, 1), ("angle_batch", -1, 1),
+])
+def test_plan_rejects_bad_fields(cm, field, value, expect):
+    d = make_desc(cm)
+    setattr(d, field, value)
+    assert plan_status(cm, d) == expect
+
+
+def test_plan_rejects_bad_sizes_and_pointers(cm):
+    assert plan_status(cm, make_desc(cm, sizes=((0, 5, 5, 5),))) == 1
+    assert plan_status(cm, make_desc(cm, sizes=((5, 5, 1025, 5),))) == 1
+    d = make_desc(cm)
+    d.h_a = None
+    assert plan_status(cm, d) == 1
+    d = make_desc(cm, angles=(0.0, 1.0))
+    d.angles_rad = None
+    assert plan_status(cm, d) == 1
+    d = make_desc(cm, angles=(float("inf"),))
+    assert plan_status(cm, d) == 1
+    h = ctypes.c_void_p()
+    assert cm._lib.cmif_plan(None, ctypes.byref(h)) == 1
+    assert cm._lib.cmif_plan(ctypes.byref(make_desc(cm)), None) == 1
+
+
+def test_plan_and_workspace_sizes(cm):
+    d = make_desc(cm, sizes=((512, 512, 512, 512),), qa=16, qb=16,
+                  angles=tuple(math.radians(2 * i) for i in range(180)))
+    h = cm.cmif_plan(d)
+    try:
+        p, s = cm.cmif_workspace_size(h)
+        assert p > 0 and s > 0 and p % 256 == 0
+        # Z of at least one angle: 256 pairs x 512 columns x 1023 rows x 8 B
+        assert s >= 256 * 512 * 1023 * 8
+    finally:
+        cm.cmif_plan_free(h)
+    dd = make_desc(cm, sizes=((64, 64, 64, 64), (30, 40, 20, 70)), qa=3, qb=5)
+    h = cm.cmif_plan(dd)
+    try:
+        assert cm.cmif_workspace_size(h)[1] > 0
+    finally:
+        cm.cmif_plan_free(h)
+
+
+def test_calls_validate_before_device_work(cm):
+    h = cm.cmif_plan(make_desc(cm))
+    try:
+        p, s = cm.cmif_workspace_size(h)
+        inp = cm.cmif_inputs()
+        out = cm.cmif_outputs()
+        lib = cm._lib
+        # workspace too small is caught on the host
+        assert lib.cmif_compute(ctypes.c_void_p(h), ctypes.byref(inp),
+                                ctypes.byref(out), None, 0, None, 0,
+                                None) == cm.CMIF_ERR_WORKSPACE_TOO_SMALL
+        # NULL inputs
+        assert lib.cmif_compute(ctypes.c_void_p(h), None, ctypes.byref(out),
+                                None, p, None, s, None) == 1
+        # NULL workspace with sufficient sizes
+        assert lib.cmif_compute(ctypes.c_void_p(h), ctypes.byref(inp),
+                                ctypes.byref(out), None, p, None, s,
+                                None) == 1
+        # misaligned workspace
+        assert lib.cmif_align(ctypes.c_void_p(h), ctypes.byref(inp),
+                              ctypes.c_void_p(256), None, None,
+                              ctypes.c_void_p(8), p, ctypes.c_void_p(256), s,
+                              None) == 1
+        # NULL best for align
+        assert lib.cmif_align(ctypes.c_void_p(h), ctypes.byref(inp), None,
+                              None, None, ctypes.c_void_p(256), p,
+                              ctypes.c_void_p(512), s, None) == 1
+        # backward on a HARD plan
+        assert lib.cmif_backward(ctypes.c_void_p(h), ctypes.byref(inp), None,
+                                 None, None, None, p, None, s,
+                                 None) == cm.CMIF_ERR_WRONG_MODE
+        assert cm.cmif_last_error() != ""
+        assert lib.cmif_workspace_size(None, None, None) == 1
+    finally:
+        cm.cmif_plan_free(h)
+    cm.cmif_plan_free(0)  # NULL is ignored
+
+
+def test_status_strings(cm):
+    seen = set()
+    for s in range(8):
+        t = cm.cmif_status_string(s)
+        assert t and t not in seen
+        seen.add(t)
+    assert cm.cmif_status_string(99) == "unknown status"
