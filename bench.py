@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Throughput of the CMIF rotation-sweep alignment on one MI355X.
+
+Workload: A, B 512x512 uint8 labels, Q_A = Q_B = 16 (256 label pairs), B a
+rotated and moved copy of A's field through a non-monotone relabelling, 180
+angles at 2 degree steps, gamma = 0.5; every angle's full 1023x1023 CMIF map
+is computed (FP32 FFTs, counts rounded to integers, FP64 entropy sums) and the
+Alg. 1 argmax is taken over displacements and angles.  One step = one
+cmif_align call over all 180 angles; value = CMIF maps per second (180 maps
+per step).
+
+The JSON line also carries:
+  roofline      the dominant kernel's algorithmic bytes per launch divided by
+                its mean launch time (HIP events on the library's stream,
+                recorded inside the timed steps), against 8 TB/s HBM;
+                traffic = measured HBM bytes per launch from the rocprofv3
+                counter summary in profiles/ when its source hash matches;
+  cpu_baseline  the CPU oracle (direct method) on a bounded sample: one
+                angle's full map on all host threads;
+  plain_fp64    the same alignment through the plain per-angle FP64
+                schedule (one angle per pass, every count map materialised)
+                and the speed-up of the batched FP32 path over it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("CMIF maps/s at 512², 16×16 labels; batched-FP32 vs "
+          "plain-FP64 speedup; HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_sha(path):
+    h = hashlib.sha256()
+    for p in sorted(path):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def hot_sources():
+    c = os.path.join(ROOT, "paper_2106_14699_amd", "csrc")
+    return [os.path.join(c, f) for f in ("k_rows.hip", "k_pair.hip",
+                                         "fft_core.h", "entropy.h",
+                                         "internal.h")]
+
+
+def read_traffic(stage):
+    """HBM bytes per launch of `stage` from the counter summary in profiles/,
+    or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_sweep512_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"source_sha:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != kernel_source_sha(hot_sources()):
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(c):
+    import oracle
+    nt = oracle.max_threads()
+    B, MB = oracle.warp_nn(c["B"], c["MB"], c["angles"][0])
+    t0 = time.perf_counter()
+    oracle.cmif_direct(c["A"], c["MA"], B, MB, c["qa"], c["qb"])
+    dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="maps/s", cores=nt, kind="oracle",
+                sample=f"1 of 180 angles (full {2 * 512 - 1}x{2 * 512 - 1} map,"
+                       f" direct method) in {dt:.1f} s on {nt} threads")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-angle FP64 comparator")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (angles would be sharded across GPUs with one "
+              "all-gather of the per-GPU best; not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2106_14699_amd as cm
+    import synth
+
+    torch.cuda.set_device(0)
+    c = synth.config3()
+    n = 512
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    A, MA, B, MB = dev(c["A"]), dev(c["MA"]), dev(c["B"]), dev(c["MB"])
+    plan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
+                   gamma=c["gamma"], precision="fp32")
+    n_maps = len(c["angles"])
+
+    first = plan.align(A, MA, B, MB)
+    for _ in range(max(args.warmup - 1, 0)):
+        plan.align(A, MA, B, MB)
+    torch.cuda.synchronize()
+
+    cm.cmif_profile_read(plan.handle)          # clear
+    cm.cmif_profile_enable(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        out = plan.align(A, MA, B, MB, sync=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    cm.cmif_profile_enable(plan.handle, False)
+    stages = cm.cmif_profile_read(plan.handle)
+    ms_per_step = ms_total / args.steps
+    value = n_maps * 1000.0 / ms_per_step
+    best = cm.best_from_bytes(bytes(out["best_raw"][0].cpu().numpy()))
+
+    dom = max(stages, key=lambda s: s["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(dom["name"])
+    roofline = dict(bound="hbm", achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=traffic, kernel=dom["name"],
+                    launches=dom["launches"],
+                    avg_launch_ms=round(avg_ms, 4),
+                    bytes_per_launch=bytes_per_launch)
+
+    plain = None
+    if not args.no_plain:
+        pplan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
+                        gamma=c["gamma"], precision="fp64", angle_batch=1,
+                        flags=cm.CMIF_FLAG_NO_GRAPH)
+        pplan.align(A, MA, B, MB)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pres = pplan.align(A, MA, B, MB)
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1)
+        pb = pres["best"][0]
+        plain = dict(ms_per_step=round(pms, 3),
+                     value=round(n_maps * 1000.0 / pms, 2), unit="maps/s",
+                     schedule="fp64 FFTs, one angle per pass, same fused kernels",
+                     same_best=(pb["angle_index"], pb["dy"], pb["dx"]) ==
+                     (best["angle_index"], best["dy"], best["dx"]))
+        del pplan
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(c)
+        cpu["value"] = round(cpu["value"], 5)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "rotation-sweep alignment: A,B 512x512 uint8, "
+                        "Q_A=Q_B=16, 180 angles at 2 deg, gamma 0.5, full "
+                        "1023x1023 CMIF map per angle",
+            "image": [n, n], "labels": [16, 16], "angles": n_maps,
+            "fft": [1024, 1024], "precision": "fp32-rounded",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": (round(plain["ms_per_step"] / ms_per_step, 3)
+                                  if plain else None),
+        "stages": {s["name"]: dict(launches=s["launches"],
+                                   ms_per_step=round(s["total_ms"] / args.steps, 3),
+                                   gbs=round(s["bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1)
+                                   if s["total_ms"] > 0 else None)
+                   for s in stages},
+        "best": dict(angle_deg=round(math.degrees(best["angle_rad"]), 3),
+                     dy=best["dy"], dx=best["dx"], mi=best["mi"], n=best["n"],
+                     truth_deg=round(c["theta_deg"], 3),
+                     truth_shift=list(c["shift"])),
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

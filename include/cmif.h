@@ -223,6 +223,30 @@ cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
                           size_t persistent_bytes, void* scratch,
                           size_t scratch_bytes, void* stream);
 
+/* Stage timing (a tracing aid).  While enabled on a plan, every kernel that
+   a call enqueues is bracketed by two hipEvents recorded on the call's
+   stream; cmif_profile_read waits for the recorded events and returns, per
+   stage, the launch count, the summed event-to-event milliseconds and the
+   algorithmic HBM bytes of those launches (the bytes the stage must move at
+   minimum: its inputs read once and its outputs written once), then clears
+   the records.  Stages: "check_labels", "fwd_rows", "fwd_cols",
+   "pair_cols", "pair_rows", "pair_counts", "argmax", "fill", "tables".
+   Disabled by default; enabling costs two event records per launch. */
+typedef struct cmif_stage_time {
+  char name[24];
+  int32_t launches;
+  int32_t reserved;
+  double total_ms;
+  double bytes;
+} cmif_stage_time;
+
+cmif_status cmif_profile_enable(cmif_plan_t plan, int32_t enable);
+
+/* Writes up to `capacity` entries to `out` (host memory) and their number to
+   *count. */
+cmif_status cmif_profile_read(cmif_plan_t plan, cmif_stage_time* out,
+                              int32_t capacity, int32_t* count);
+
 /* Static description of a status code. */
 const char* cmif_status_string(cmif_status status);
 

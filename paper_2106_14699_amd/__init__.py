@@ -39,6 +39,7 @@ CMIF_FLAG_SAVE_FOR_BACKWARD = 1 << 2
 
 EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_compute", "cmif_align", "cmif_backward",
+            "cmif_profile_enable", "cmif_profile_read",
             "cmif_status_string", "cmif_last_error")
 
 _P = ctypes.c_void_p
@@ -88,6 +89,12 @@ class cmif_outputs(ctypes.Structure):
                 ("best", _P), ("per_angle", _P), ("stats", _P)]
 
 
+class cmif_stage_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class CmifError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str = ""):
         self.status = status
@@ -101,7 +108,7 @@ def _load_lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"libcmif.so not found at {LIB_PATH}; build it with "
-            "`python -m paper_2106_14699_amd.build` (there is no fallback)")
+            "`python paper_2106_14699_amd/build.py` (there is no fallback)")
     lib = ctypes.CDLL(LIB_PATH)
     S = ctypes.c_size_t
     lib.cmif_plan.argtypes = [ctypes.POINTER(cmif_plan_desc), ctypes.POINTER(_P)]
@@ -119,6 +126,12 @@ def _load_lib():
     lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
                                   _PP, _P, S, _P, S, _P]
     lib.cmif_backward.restype = ctypes.c_int
+    lib.cmif_profile_enable.argtypes = [_P, ctypes.c_int32]
+    lib.cmif_profile_enable.restype = ctypes.c_int
+    lib.cmif_profile_read.argtypes = [_P, ctypes.POINTER(cmif_stage_time),
+                                      ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]
+    lib.cmif_profile_read.restype = ctypes.c_int
     lib.cmif_status_string.argtypes = [ctypes.c_int]
     lib.cmif_status_string.restype = ctypes.c_char_p
     lib.cmif_last_error.argtypes = []
@@ -184,6 +197,24 @@ def cmif_backward(plan, inputs, grad_mi, grad_a, grad_b, persistent,
                               grad_b, _P(persistent), persistent_bytes,
                               _P(scratch), scratch_bytes, _P(stream)),
            "cmif_backward")
+
+
+def cmif_profile_enable(plan: int, enable: bool) -> None:
+    _check(_lib.cmif_profile_enable(_P(plan), 1 if enable else 0),
+           "cmif_profile_enable")
+
+
+def cmif_profile_read(plan: int) -> list[dict]:
+    """Per-stage launch counts, summed event milliseconds and algorithmic
+    bytes recorded since the last read (waits for the recorded events)."""
+    cap = 32
+    buf = (cmif_stage_time * cap)()
+    n = ctypes.c_int32()
+    _check(_lib.cmif_profile_read(_P(plan), buf, cap, ctypes.byref(n)),
+           "cmif_profile_read")
+    return [dict(name=buf[i].name.decode(), launches=buf[i].launches,
+                 total_ms=buf[i].total_ms, bytes=buf[i].bytes)
+            for i in range(n.value)]
 
 
 # -- torch convenience layer ----------------------------------------------------

@@ -1,5 +1,8 @@
 """Build libcmif.so for gfx950 in-tree (hipcc, one object per source file,
-compiled in parallel, then linked).  Usage: python -m paper_2106_14699_amd.build
+compiled in parallel, then linked).
+
+Usage: python paper_2106_14699_amd/build.py  (run by path: importing the
+package loads the library this script builds).
 """
 
 from __future__ import annotations

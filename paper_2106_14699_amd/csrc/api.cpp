@@ -49,6 +49,38 @@ struct ScratchLayout {
   size_t xa, fa, xb, fb, z, mi, n, maxn, flags, partial, running, stats, end;
 };
 
+enum Stage {
+  ST_CHECK, ST_FWD_ROWS, ST_FWD_COLS, ST_PAIR_COLS, ST_PAIR_ROWS,
+  ST_PAIR_COUNTS, ST_ARGMAX, ST_FILL, ST_TABLES, ST_COUNT
+};
+const char* const kStageNames[ST_COUNT] = {
+    "check_labels", "fwd_rows", "fwd_cols", "pair_cols", "pair_rows",
+    "pair_counts", "argmax", "fill", "tables"};
+
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace
 
 struct cmif_plan_s {
@@ -65,6 +97,7 @@ struct cmif_plan_s {
   size_t scratch_bytes = 0;
   int nchunks_max = 1;
   bool device_checked = false;
+  Profiler prof;
 };
 
 namespace {
@@ -144,6 +177,36 @@ struct DeviceGuard {
                                        hipGetErrorString(_e));              \
   } while (0)
 
+// Runs one launch; with profiling on, brackets it with events on `st`.
+template <class F>
+cmif_status launch_stage(cmif_plan_s& P, hipStream_t st, int stage,
+                         double bytes, const char* what, F&& launch) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (P.prof.on) {
+    ea = P.prof.take();
+    eb = P.prof.take();
+    if (!ea || !eb) return fail(CMIF_ERR_DEVICE, "hipEventCreate failed");
+    if (hipEventRecord(ea, st) != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, "hipEventRecord failed");
+  }
+  const hipError_t e = launch();
+  if (e != hipSuccess)
+    return fail(CMIF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  if (P.prof.on) {
+    if (hipEventRecord(eb, st) != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, "hipEventRecord failed");
+    P.prof.recs.push_back(ProfRec{stage, ea, eb, bytes});
+  }
+  return CMIF_OK;
+}
+
+#define STAGE(stage, bytes, call)                                            \
+  do {                                                                       \
+    cmif_status _s = launch_stage(P, st, (stage), (double)(bytes), #call,   \
+                                  [&]() { return (call); });                 \
+    if (_s != CMIF_OK) return _s;                                            \
+  } while (0)
+
 struct CallOutputs {
   double* mi = nullptr;          // caller map for this pair or null
   int32_t* n = nullptr;
@@ -155,7 +218,7 @@ struct CallOutputs {
 };
 
 template <typename T>
-cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
+cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
                      const uint8_t* ma, const uint8_t* lb, const uint8_t* mb,
                      const CallOutputs& o, uint8_t* pers, uint8_t* scr,
                      hipStream_t st) {
@@ -186,8 +249,12 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
   cmif_best* running = reinterpret_cast<cmif_best*>(scr + L.running);
   cmif_stats* stats = o.stats;
 
-  HIP_TRY(launch_check_labels(la, ma, (long long)g.ha * g.wa, qa, stats, st));
-  HIP_TRY(launch_check_labels(lb, mb, (long long)g.hb * g.wb, qb, stats, st));
+  if (stats) {
+    STAGE(ST_CHECK, 2.0 * g.ha * g.wa,
+          launch_check_labels(la, ma, (long long)g.ha * g.wa, qa, stats, st));
+    STAGE(ST_CHECK, 2.0 * g.hb * g.wb,
+          launch_check_labels(lb, mb, (long long)g.hb * g.wb, qb, stats, st));
+  }
 
   // forward transforms of A's level sets (identity resampling)
   {
@@ -195,13 +262,15 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
     a.lab = la; a.msk = ma; a.H = g.ha; a.W = g.wa; a.Q = qa; a.nb = 1;
     a.rot.c[0] = 65536; a.rot.s[0] = 0;
     a.xrow = xa; a.angle_stride = 0; a.tw = tw_w;
-    HIP_TRY(launch_fwd_rows<T>(g.pw, a, st));
+    STAGE(ST_FWD_ROWS, 2.0 * g.ha * g.wa + (double)qa * half * g.ha * sizeof(CT),
+          launch_fwd_rows<T>(g.pw, a, st));
     FwdColsArgs<T> c{};
     c.xrow = xa; c.H = g.ha; c.tiles = tiles; c.Q = qa; c.nb = 1;
     c.x_angle_stride = 0; c.x_label_stride = (long long)half * g.ha;
     c.F = fa; c.f_angle_stride = 0; c.f_label_stride = (long long)half * g.ph;
     c.tw = tw_h;
-    HIP_TRY(launch_fwd_cols<T>(g.ph, c, st));
+    STAGE(ST_FWD_COLS, (double)qa * half * (g.ha + g.ph) * sizeof(CT),
+          launch_fwd_cols<T>(g.ph, c, st));
   }
   const int nang = (int)P.angles.size();
   const long long map_stride = (long long)g.sh * g.sw;
@@ -214,17 +283,20 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
     r.lab = lb; r.msk = mb; r.H = g.hb; r.W = g.wb; r.Q = qb; r.nb = nb;
     for (int b = 0; b < nb; ++b) { r.rot.c[b] = P.rc[a0 + b]; r.rot.s[b] = P.rs[a0 + b]; }
     r.xrow = xb; r.angle_stride = (long long)qb * half * g.hb; r.tw = tw_w;
-    HIP_TRY(launch_fwd_rows<T>(g.pw, r, st));
+    STAGE(ST_FWD_ROWS, nb * (2.0 * g.hb * g.wb + (double)qb * half * g.hb * sizeof(CT)),
+          launch_fwd_rows<T>(g.pw, r, st));
     FwdColsArgs<T> c{};
     c.xrow = xb; c.H = g.hb; c.tiles = tiles; c.Q = qb; c.nb = nb;
     c.x_angle_stride = (long long)qb * half * g.hb;
     c.x_label_stride = (long long)half * g.hb;
     c.F = fb; c.f_angle_stride = (long long)qb * half * g.ph;
     c.f_label_stride = (long long)half * g.ph; c.tw = tw_h;
-    HIP_TRY(launch_fwd_cols<T>(g.ph, c, st));
+    STAGE(ST_FWD_COLS, nb * (double)qb * half * (g.hb + g.ph) * sizeof(CT),
+          launch_fwd_cols<T>(g.ph, c, st));
 
-    HIP_TRY(launch_fill_u32(maxn, 0u, nb, st));
-    HIP_TRY(launch_fill_u32(flags, 0u, (long long)nb * qa * qb, st));
+    STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(maxn, 0u, nb, st));
+    STAGE(ST_FILL, 4.0 * nb * qa * qb,
+          launch_fill_u32(flags, 0u, (long long)nb * qa * qb, st));
 
     PairColsArgs<T> pc{};
     pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
@@ -234,7 +306,11 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
     pc.tiles = tiles; pc.nb = nb; pc.Z = z;
     pc.z_angle_stride = (long long)qa * qb * half * g.sh;
     pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h;
-    HIP_TRY(launch_pair_cols<T>(g.ph, pc, st));
+    // A's spectra once per launch, B's once per angle, every pair's columns
+    STAGE(ST_PAIR_COLS,
+          (double)qa * half * g.ph * sizeof(CT) +
+              nb * ((double)qb * half * g.ph + (double)qa * qb * half * g.sh) * sizeof(CT),
+          launch_pair_cols<T>(g.ph, pc, st));
 
     double* mi_ptr = o.mi ? o.mi + a0 * map_stride : mi_s;
     int32_t* n_ptr = o.n ? o.n + a0 * map_stride : n_s;
@@ -245,7 +321,10 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
     pr.logtab = logtab; pr.mi = mi_ptr; pr.mi_angle_stride = map_stride;
     pr.n = n_ptr; pr.n_angle_stride = map_stride; pr.maxn = maxn; pr.flags = flags;
     pr.stats = stats;
-    HIP_TRY(launch_pair_rows<T>(g.pw, pr, st));
+    // every pair's columns read once, MI and N maps written once
+    STAGE(ST_PAIR_ROWS,
+          nb * ((double)qa * qb * half * g.sh * sizeof(CT) + 12.0 * g.sh * g.sw),
+          launch_pair_rows<T>(g.pw, pr, st));
     if (o.counts || o.digest) {
       PairCountsArgs<T> pk{};
       pk.Z = z; pk.z_angle_stride = pc.z_angle_stride; pk.z_pair_stride = pc.z_pair_stride;
@@ -254,7 +333,9 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
       pk.counts = o.counts ? o.counts + (long long)a0 * qa * qb * map_stride : nullptr;
       pk.counts_angle_stride = (long long)qa * qb * map_stride;
       pk.digest = o.digest ? o.digest + (long long)a0 * qa * qb : nullptr;
-      HIP_TRY(launch_pair_counts<T>(g.pw, pk, st));
+      STAGE(ST_PAIR_COUNTS,
+            nb * (double)qa * qb * (half * g.sh * sizeof(CT) + (o.counts ? 4.0 * g.sh * g.sw : 0.0)),
+            launch_pair_counts<T>(g.pw, pk, st));
     }
 
     if (want_best) {
@@ -262,7 +343,7 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
       am.mi = mi_ptr; am.n = n_ptr; am.angle_stride = map_stride; am.maxn = maxn;
       am.sh = g.sh; am.sw = g.sw; am.nb = nb; am.rows_per_chunk = rpc;
       am.nchunks = nchunks; am.gamma = P.d.gamma; am.partial = partial;
-      HIP_TRY(launch_argmax(am, st));
+      STAGE(ST_ARGMAX, nb * 12.0 * g.sh * g.sw, launch_argmax(am, st));
       ArgmaxFinalArgs af{};
       af.partial = partial; af.nb = nb; af.nchunks = nchunks; af.sw = g.sw;
       af.ha = g.ha; af.wa = g.wa; af.angle0 = a0;
@@ -270,7 +351,8 @@ cmif_status run_pair(const cmif_plan_s& P, int p, const uint8_t* la,
       af.per_angle = o.per_angle; af.running = running;
       af.first_batch = a0 == 0; af.best_out = o.best;
       af.last_batch = a0 + nb >= nang;
-      HIP_TRY(launch_argmax_final(af, st));
+      STAGE(ST_ARGMAX, nb * (double)nchunks * sizeof(ArgPartial),
+            launch_argmax_final(af, st));
     }
   }
   return CMIF_OK;
@@ -305,20 +387,27 @@ cmif_status run_hard(cmif_plan_s* P, const cmif_inputs* in,
   uint8_t* pb = static_cast<uint8_t*>(pers);
   uint8_t* sb = static_cast<uint8_t*>(scr);
   // tables
+  cmif_plan_s& PP = *P;
   for (size_t i = 0; i < P->plens.size(); ++i) {
     const int L = P->plens[i];
-    HIP_TRY(launch_init_tables(pb + P->tw_off[i],
-                               pb + P->tw_off[i] + (size_t)L * sizeof(float2), L,
-                               i == 0 ? reinterpret_cast<double*>(pb + P->logtab_off)
-                                      : nullptr,
-                               st));
+    cmif_status s = launch_stage(
+        PP, st, ST_TABLES, 24.0 * L, "launch_init_tables", [&]() {
+          return launch_init_tables(
+              pb + P->tw_off[i], pb + P->tw_off[i] + (size_t)L * sizeof(float2), L,
+              i == 0 ? reinterpret_cast<double*>(pb + P->logtab_off) : nullptr, st);
+        });
+    if (s != CMIF_OK) return s;
   }
   const int nang = (int)P->angles.size();
   if (out && out->digest) {
     for (int p = 0; p < np; ++p)
-      if (out->digest[p])
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(out->digest[p]), 0u,
-                                2LL * nang * P->d.q_a * P->d.q_b, st));
+      if (out->digest[p]) {
+        const long long nw = 2LL * nang * P->d.q_a * P->d.q_b;
+        cmif_status s = launch_stage(PP, st, ST_FILL, 4.0 * nw, "fill digest", [&]() {
+          return launch_fill_u32(reinterpret_cast<uint32_t*>(out->digest[p]), 0u, nw, st);
+        });
+        if (s != CMIF_OK) return s;
+      }
   }
   for (int p = 0; p < np; ++p) {
     CallOutputs o;
@@ -364,6 +453,44 @@ const char* cmif_status_string(cmif_status s) {
 }
 
 const char* cmif_last_error(void) { return g_err.c_str(); }
+
+cmif_status cmif_profile_enable(cmif_plan_t plan, int32_t enable) {
+  g_err.clear();
+  if (!plan) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan");
+  plan->prof.on = enable != 0;
+  return CMIF_OK;
+}
+
+cmif_status cmif_profile_read(cmif_plan_t plan, cmif_stage_time* out,
+                              int32_t capacity, int32_t* count) {
+  g_err.clear();
+  if (!plan || !count || (capacity > 0 && !out))
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL argument");
+  cmif_stage_time acc[ST_COUNT];
+  std::memset(acc, 0, sizeof(acc));
+  for (int s = 0; s < ST_COUNT; ++s)
+    std::snprintf(acc[s].name, sizeof(acc[s].name), "%s", kStageNames[s]);
+  for (const ProfRec& r : plan->prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, "hipEventSynchronize failed");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, "hipEventElapsedTime failed");
+    acc[r.stage].launches += 1;
+    acc[r.stage].total_ms += ms;
+    acc[r.stage].bytes += r.bytes;
+  }
+  plan->prof.recs.clear();
+  plan->prof.used = 0;
+  int n = 0;
+  for (int s = 0; s < ST_COUNT; ++s) {
+    if (acc[s].launches == 0) continue;
+    if (n < capacity) out[n] = acc[s];
+    ++n;
+  }
+  *count = n < capacity ? n : capacity;
+  return CMIF_OK;
+}
 
 cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   g_err.clear();
