@@ -92,6 +92,7 @@ struct cmif_plan_s {
   std::vector<int> plens;       // distinct FFT lengths
   std::vector<size_t> tw_off;   // per plens entry: FP32 table, FP64 follows
   size_t logtab_off = 0;
+  size_t xlog_off = 0;
   size_t persistent_bytes = 0;
   ScratchLayout lay{};
   size_t scratch_bytes = 0;
@@ -236,6 +237,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
   const CT* tw_h = reinterpret_cast<const CT*>(
       pers + P.tw_off[ih] + (fp64 ? (size_t)g.ph * sizeof(float2) : 0));
   const double* logtab = reinterpret_cast<const double*>(pers + P.logtab_off);
+  const double* xlogtab = reinterpret_cast<const double*>(pers + P.xlog_off);
   CT* xa = reinterpret_cast<CT*>(scr + L.xa);
   CT* fa = reinterpret_cast<CT*>(scr + L.fa);
   CT* xb = reinterpret_cast<CT*>(scr + L.xb);
@@ -318,7 +320,8 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
     pr.QA = qa; pr.QB = qb; pr.wa = g.wa; pr.wb = g.wb;
     pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb; pr.tw = tw_w;
-    pr.logtab = logtab; pr.mi = mi_ptr; pr.mi_angle_stride = map_stride;
+    pr.logtab = logtab; pr.xlogtab = xlogtab; pr.rows_per_wg = 2;
+    pr.mi = mi_ptr; pr.mi_angle_stride = map_stride;
     pr.n = n_ptr; pr.n_angle_stride = map_stride; pr.maxn = maxn; pr.flags = flags;
     pr.stats = stats;
     // every pair's columns read once, MI and N maps written once
@@ -394,7 +397,8 @@ cmif_status run_hard(cmif_plan_s* P, const cmif_inputs* in,
         PP, st, ST_TABLES, 24.0 * L, "launch_init_tables", [&]() {
           return launch_init_tables(
               pb + P->tw_off[i], pb + P->tw_off[i] + (size_t)L * sizeof(float2), L,
-              i == 0 ? reinterpret_cast<double*>(pb + P->logtab_off) : nullptr, st);
+              i == 0 ? reinterpret_cast<double*>(pb + P->logtab_off) : nullptr,
+              i == 0 ? reinterpret_cast<double*>(pb + P->xlog_off) : nullptr, st);
         });
     if (s != CMIF_OK) return s;
   }
@@ -587,6 +591,8 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   }
   P->logtab_off = o;
   o += up256(512 * sizeof(double));
+  P->xlog_off = o;
+  o += up256(kXlogN * sizeof(double));
   P->persistent_bytes = o;
   size_t smax = 0;
   for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);

@@ -11,10 +11,12 @@
 // above, the reads of every stage are exactly the lane's own registers, and
 // the last stage lands in natural order without an exchange.
 //
-// Radices are chosen greedily, r = min(16, R, N/Ns), so N = 1024 runs as
-// 16 x 16 x 4 with two LDS exchanges.  Twiddles come from a table
-// tw[t] = exp(+2 pi i t / N) computed in FP64 (no recurrences); DIR = -1
-// (forward) uses its conjugate.  Transforms are unnormalised both ways.
+// Radices are chosen greedily, r = min(16, R, N/Ns) (R = N/TEAM points per
+// lane), e.g. N = 1024 over 128 lanes runs as 8 x 8 x 8 x 2 with three LDS
+// exchanges.  Twiddles come from a table tw[t] = exp(+2 pi i t / N) computed
+// in FP64 (no recurrences); each lane keeps the entries it needs in
+// registers; DIR = -1 (forward) uses their conjugates.  Transforms are
+// unnormalised both ways.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -140,16 +142,90 @@ __device__ __forceinline__ void team_sync() {
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
-// One Stockham stage with Ns = NS, then recurse into the next.
-template <typename T, int N, int TEAM, int DIR, int NS>
-__device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
-                                          const C2<T>* tw, int lane) {
+// Stage plan: radix of the stage with Ns = ns, and how many twiddles one
+// lane needs for all stages (R/r butterflies x (r - 1) twiddles per stage with
+// Ns > 1).  The twiddles of a lane are the same for every transform it does,
+// so kernels load them once (fft_load_twiddles) and keep them in registers.
+constexpr int stage_radix(int n, int team, int ns) {
+  return cmin(16, cmin(n / team, n / ns));
+}
+
+constexpr int fft_tw_count_from(int n, int team, int ns) {
+  return ns >= n ? 0
+                 : (ns > 1 ? (n / team / stage_radix(n, team, ns)) *
+                                 (stage_radix(n, team, ns) - 1)
+                           : 0) +
+                       fft_tw_count_from(n, team, ns * stage_radix(n, team, ns));
+}
+
+template <int N, int TEAM>
+constexpr int fft_tw_count() { return fft_tw_count_from(N, TEAM, 1); }
+
+template <typename T, int N, int TEAM>
+struct FftTw {
+  C2<T> w[fft_tw_count<N, TEAM>() > 0 ? fft_tw_count<N, TEAM>() : 1];
+};
+
+template <typename T, int N, int TEAM, int NS, int OFF>
+__device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM>& f,
+                                             const C2<T>* __restrict__ tw,
+                                             int lane) {
   constexpr int R = N / TEAM;
-  constexpr int REM = N / NS;
-  constexpr int RAD = cmin(16, cmin(R, REM));
+  constexpr int RAD = stage_radix(N, TEAM, NS);
   constexpr bool LAST = (NS * RAD == N);
   constexpr int BPL = R / RAD;
   constexpr int TSTRIDE = N / (NS * RAD);
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int t = 0; t < BPL; ++t) {
+      const int k = (lane + TEAM * t) & (NS - 1);
+#pragma unroll
+      for (int m = 1; m < RAD; ++m)
+        f.w[OFF + t * (RAD - 1) + (m - 1)] = tw[m * k * TSTRIDE];
+    }
+  }
+  if constexpr (!LAST)
+    fft_tw_stage<T, N, TEAM, NS * RAD,
+                 OFF + (NS > 1 ? BPL * (RAD - 1) : 0)>(f, tw, lane);
+}
+
+// Fills a lane's twiddles from the table tw[t] = exp(+2 pi i t / N).
+template <typename T, int N, int TEAM>
+__device__ __forceinline__ void fft_load_twiddles(FftTw<T, N, TEAM>& f,
+                                                  const C2<T>* __restrict__ tw,
+                                                  int lane) {
+  fft_tw_stage<T, N, TEAM, 1, 0>(f, tw, lane);
+}
+
+// Twiddle source reading the N-entry table exp(+2 pi i t/N) from LDS (or any
+// memory) at every stage, for kernels whose register budget is tight.
+template <typename T, int N, int TEAM>
+struct FftTwTable {
+  const C2<T>* tab;
+};
+
+template <typename T, int N, int TEAM, int NS, int RAD, int OFF>
+__device__ __forceinline__ C2<T> tw_get(const FftTw<T, N, TEAM>& f, int t, int m,
+                                        int k) {
+  (void)k;
+  return f.w[OFF + t * (RAD - 1) + (m - 1)];
+}
+
+template <typename T, int N, int TEAM, int NS, int RAD, int OFF>
+__device__ __forceinline__ C2<T> tw_get(const FftTwTable<T, N, TEAM>& f, int t,
+                                        int m, int k) {
+  (void)t;
+  return f.tab[m * k * (N / (NS * RAD))];
+}
+
+// One Stockham stage with Ns = NS (twiddles from offset OFF), then the next.
+template <typename T, int N, int TEAM, int DIR, int NS, int OFF, class TWS>
+__device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
+                                          const TWS& f, int lane) {
+  constexpr int R = N / TEAM;
+  constexpr int RAD = stage_radix(N, TEAM, NS);
+  constexpr bool LAST = (NS * RAD == N);
+  constexpr int BPL = R / RAD;
 #pragma unroll
   for (int t = 0; t < BPL; ++t) {
     const int j = lane + TEAM * t;
@@ -160,7 +236,7 @@ __device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
     if constexpr (NS > 1) {
 #pragma unroll
       for (int m = 1; m < RAD; ++m) {
-        C2<T> w = tw[m * k * TSTRIDE];
+        C2<T> w = tw_get<T, N, TEAM, NS, RAD, OFF>(f, t, m, k);
         if constexpr (DIR < 0) w.y = -w.y;
         x[m] = cmul<T>(x[m], w);
       }
@@ -180,19 +256,21 @@ __device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
 #pragma unroll
     for (int q = 0; q < R; ++q) v[q] = lds[lpad(lane + TEAM * q)];
     team_sync<TEAM>();
-    fft_stage<T, N, TEAM, DIR, NS * RAD>(v, lds, tw, lane);
+    fft_stage<T, N, TEAM, DIR, NS * RAD, OFF + (NS > 1 ? BPL * (RAD - 1) : 0),
+              TWS>(v, lds, f, lane);
   }
 }
 
 // In-place unnormalised DFT of length N over a team: DIR = -1 forward
 // (exp(-2 pi i jk/N)), +1 inverse.  lds: lds_elems(N) elements private to
-// the team; tw: N-entry table exp(+2 pi i t/N) (global or LDS).
-template <typename T, int N, int TEAM, int DIR>
+// the team; f: the lane's twiddles in registers (FftTw, fft_load_twiddles)
+// or the N-entry table (FftTwTable).
+template <typename T, int N, int TEAM, int DIR, class TWS>
 __device__ __forceinline__ void team_fft(C2<T> (&v)[N / TEAM], C2<T>* lds,
-                                         const C2<T>* tw, int lane) {
+                                         const TWS& f, int lane) {
   static_assert(N % TEAM == 0 && N / TEAM >= 2, "team too large for N");
   static_assert((N & (N - 1)) == 0, "power-of-two lengths only");
-  fft_stage<T, N, TEAM, DIR, 1>(v, lds, tw, lane);
+  fft_stage<T, N, TEAM, DIR, 1, 0, TWS>(v, lds, f, lane);
 }
 
 }  // namespace cmif

@@ -22,6 +22,7 @@ namespace cmif {
 
 constexpr int kMaxBatch = 16;  // angles per pipeline pass (kernel argument)
 constexpr int kMinP = 128;
+constexpr int kXlogN = 2048;   // c log2 c tabulated for integer c < kXlogN
 constexpr int kMaxP = 2048;
 
 struct RotArgs {
@@ -50,6 +51,16 @@ template <typename T>
 constexpr int col_team_for(int p) {
   return team_for(p) * tile_width<T>() <= 1024 ? team_for(p)
                                                : 1024 / tile_width<T>();
+}
+
+// Column swizzle of a [rows][TW] LDS staging tile: element (row, col) lives
+// at row*TW + (col ^ stage_swz(row)).  The swizzle is a multiple of
+// 16 B / sizeof(element) so 16-byte vectors of a row stay contiguous, and
+// writing one column for consecutive rows spreads over the banks (at most
+// 2-way conflicts instead of TW-way).
+template <int TW>
+__host__ __device__ constexpr int stage_swz(int row) {
+  return TW == 8 ? ((row >> 1) & 3) << 1 : (row >> 1) & (TW - 1);
 }
 
 // Map row of a circular correlation row y (P_h periodic): chi_y = y for

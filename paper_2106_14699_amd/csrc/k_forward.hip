@@ -39,6 +39,8 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
   const int lane = threadIdx.x % TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
 
+  FftTw<T, P, TEAM> ftw;
+  fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
   const long long c = rot.c[beta], s = rot.s[beta];
   const long long one = 65536;
   uint8_t lv[R];
@@ -76,7 +78,7 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
 #pragma unroll
     for (int q = 0; q < R; ++q)
       v[q] = mk<T>(lv[q] == a0 ? (T)1 : (T)0, lv[q] == a1 ? (T)1 : (T)0);
-    team_fft<T, P, TEAM, -1>(v, lds, tw, lane);
+    team_fft<T, P, TEAM, -1>(v, lds, ftw, lane);
 #pragma unroll
     for (int q = 0; q < R; ++q) lds[lpad(lane + TEAM * q)] = v[q];
     team_sync<TEAM>();
@@ -123,22 +125,27 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
   const int lane = threadIdx.x % TEAM;
   const C2<T>* src = xrow + beta * x_angle_stride + lbl * x_label_stride +
                      (long long)t * H * TW;
-  // coalesced tile load: H rows of one 64-byte segment each
+  FftTw<T, P, TEAM> ftw;
+  fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
+  // coalesced tile load (H rows of one 64-byte segment each, 16-byte
+  // vectors) into a column-swizzled LDS tile for the column reads below
   {
-    const int n16 = H * TW * (int)sizeof(C2<T>) / 16;
+    constexpr int EV = 16 / (int)sizeof(C2<T>);  // elements per vector
     const float4* s4 = reinterpret_cast<const float4*>(src);
-    float4* d4 = reinterpret_cast<float4*>(smem);
-    for (int i = threadIdx.x; i < n16; i += blockDim.x) d4[i] = s4[i];
+    for (int e = threadIdx.x; e < H * TW / EV; e += blockDim.x) {
+      const int y = (e * EV) / TW, col = (e * EV) % TW;
+      *reinterpret_cast<float4*>(&smem[y * TW + (col ^ stage_swz<TW>(y))]) = s4[e];
+    }
   }
   __syncthreads();
   C2<T> v[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int y = lane + TEAM * q;
-    v[q] = y < H ? smem[y * TW + team] : mk<T>((T)0, (T)0);
+    v[q] = y < H ? smem[y * TW + (team ^ stage_swz<TW>(y))] : mk<T>((T)0, (T)0);
   }
   __syncthreads();
-  team_fft<T, P, TEAM, -1>(v, smem + team * lds_elems(P), tw, lane);
+  team_fft<T, P, TEAM, -1>(v, smem + team * lds_elems(P), ftw, lane);
   C2<T>* dst = F + beta * f_angle_stride + lbl * f_label_stride +
                (long long)(t * TW + team) * P;
 #pragma unroll

@@ -9,8 +9,10 @@ namespace cmif {
 
 // tw[t] = exp(+2 pi i t / P) evaluated in FP64 with sincospi (exact argument
 // reduction of t/P), stored in FP32 and FP64; logtab[j] = log2(1 + j/256),
-// logtab[256 + j] = 1 / (1 + j/256).
-__global__ void k_init_tables(float2* tw32, double2* tw64, int P, double* logtab) {
+// logtab[256 + j] = 1 / (1 + j/256); xlogtab[c] = c log2 c for c < kXlogN
+// (0 for c = 0, 1).
+__global__ void k_init_tables(float2* tw32, double2* tw64, int P, double* logtab,
+                              double* xlogtab) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < P) {
     double s, c;
@@ -23,13 +25,14 @@ __global__ void k_init_tables(float2* tw32, double2* tw64, int P, double* logtab
     logtab[t] = log2(m);
     logtab[256 + t] = 1.0 / m;
   }
+  if (xlogtab && t < kXlogN) xlogtab[t] = t <= 1 ? 0.0 : (double)t * log2((double)t);
 }
 
 hipError_t launch_init_tables(void* tw32, void* tw64, int P, double* logtab,
-                              hipStream_t st) {
-  const int n = P > 256 ? P : 256;
+                              double* xlogtab, hipStream_t st) {
+  const int n = P > kXlogN ? P : kXlogN;
   hipLaunchKernelGGL(k_init_tables, dim3((n + 255) / 256), dim3(256), 0, st,
-                     (float2*)tw32, (double2*)tw64, P, logtab);
+                     (float2*)tw32, (double2*)tw64, P, logtab, xlogtab);
   return hipGetLastError();
 }
 

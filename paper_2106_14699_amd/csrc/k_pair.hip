@@ -22,40 +22,77 @@ __device__ __forceinline__ void unpack0(C2<T> w, C2<T> wm, C2<T>& g0, C2<T>& g1)
   g1 = mk<T>((w.y + wm.y) * (T)0.5, (wm.x - w.x) * (T)0.5);
 }
 
+// LDS of the column kernel: the teams' exchange buffers (re-used as the
+// staging tile) and, when it fits, the twiddle table (otherwise every lane
+// keeps its twiddles in registers).
+template <typename T, int P>
+constexpr size_t pair_cols_exch_bytes() {
+  return (size_t)tile_width<T>() * lds_elems(P) * sizeof(C2<T>);
+}
+template <typename T, int P>
+constexpr bool pair_cols_lds_twiddles() {
+  return pair_cols_exch_bytes<T, P>() + (size_t)P * sizeof(C2<T>) <= 160 * 1024;
+}
+
+// Staging + store of one b's TW columns: rows i of the tile leave as 16-byte
+// vectors into Z[a*Q_B+b][tile][i][TW].
 template <typename T, int P, int TEAM>
-__global__ void __launch_bounds__(tile_width<T>() * TEAM)
-k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
-            const C2<T>* __restrict__ FB, long long fb_angle_stride,
-            long long fb_label_stride, int QB, int ha, int hb, int sh,
-            C2<T>* __restrict__ Z, long long z_angle_stride,
-            long long z_pair_stride, const C2<T>* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
+__device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* smem,
+                                                C2<T>* __restrict__ zp, int ha,
+                                                int hb, int sh, int team,
+                                                int lane) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
-  const int t = blockIdx.x, a = blockIdx.y, beta = blockIdx.z;
-  const int team = threadIdx.x / TEAM;
-  const int lane = threadIdx.x % TEAM;
-  const int c = t * TW + team;
-  C2<T>* lds = smem + team * lds_elems(P);
+  constexpr int EV = 16 / (int)sizeof(C2<T>);
+  __syncthreads();  // every team is done with its exchange buffer
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = circ_to_map(lane + TEAM * q, P, ha, hb);
+    if (i >= 0) smem[i * TW + (team ^ stage_swz<TW>(i))] = v[q];
+  }
+  __syncthreads();
+  float4* z4 = reinterpret_cast<float4*>(zp);
+  for (int e = threadIdx.x; e < sh * TW / EV; e += blockDim.x) {
+    const int i = (e * EV) / TW, col = (e * EV) % TW;
+    z4[e] = *reinterpret_cast<const float4*>(&smem[i * TW + (col ^ stage_swz<TW>(i))]);
+  }
+  __syncthreads();
+}
 
-  const C2<T>* fa_col = FA + a * fa_label_stride + (long long)c * P;
+template <typename T, int P, int TEAM, class TWS>
+__device__ __forceinline__ void pair_cols_run(
+    const C2<T>* __restrict__ fa_col, const C2<T>* __restrict__ fb_base,
+    long long fb_label_stride, int QB, int a, int ha, int hb, int sh,
+    C2<T>* __restrict__ z_base, long long z_pair_stride, const TWS& ftw,
+    C2<T>* smem, int c, int team, int lane) {
+  constexpr int R = P / TEAM;
+  C2<T>* lds = smem + team * lds_elems(P);
   C2<T> fa[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) fa[q] = fa_col[lane + TEAM * q];
-  const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
-  C2<T>* z_base = Z + beta * z_angle_stride + (long long)t * sh * TW;
-  const int n16 = sh * TW * (int)sizeof(C2<T>) / 16;
-
-  for (int b = 0; b < QB; ++b) {
-    const C2<T>* fb_col = fb_base + b * fb_label_stride;
-    C2<T> v[R];
-    if (c != 0) {
+  if (c != 0) {
+    // software pipeline: the next b's column is in flight during this FFT
+    C2<T> fbn[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[q] = cmulc<T>(fa[q], fb_col[lane + TEAM * q]);
-    } else {
-      // slot 0 packs the k_x = 0 and k_x = P_w/2 columns (both Hermitian);
-      // the mirrored values are re-read so no extra registers stay live
+    for (int q = 0; q < R; ++q) fbn[q] = fb_base[lane + TEAM * q];
+    for (int b = 0; b < QB; ++b) {
+      C2<T> v[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = cmulc<T>(fa[q], fbn[q]);
+      if (b + 1 < QB) {
+        const C2<T>* fb_next = fb_base + (b + 1) * fb_label_stride;
+#pragma unroll
+        for (int q = 0; q < R; ++q) fbn[q] = fb_next[lane + TEAM * q];
+      }
+      team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
+      pair_cols_store<T, P, TEAM>(v, smem, z_base + (long long)(a * QB + b) * z_pair_stride,
+                                  ha, hb, sh, team, lane);
+    }
+  } else {
+    // slot 0 packs the k_x = 0 and k_x = P_w/2 columns (both Hermitian)
+    for (int b = 0; b < QB; ++b) {
+      const C2<T>* fb_col = fb_base + b * fb_label_stride;
+      C2<T> v[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int k = lane + TEAM * q;
@@ -67,21 +104,42 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
         const C2<T> y1 = cmulc<T>(ga1, gb1);     // Hermitian in k
         v[q] = mk<T>(y0.x - y1.y, y0.y + y1.x);  // y0 + i y1
       }
+      team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
+      pair_cols_store<T, P, TEAM>(v, smem, z_base + (long long)(a * QB + b) * z_pair_stride,
+                                  ha, hb, sh, team, lane);
     }
-    team_fft<T, P, TEAM, +1>(v, lds, tw, lane);
-    __syncthreads();  // every team is done with its exchange buffer
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = circ_to_map(lane + TEAM * q, P, ha, hb);
-      if (i >= 0) smem[i * TW + team] = v[q];
-    }
+  }
+}
+
+template <typename T, int P, int TEAM>
+__global__ void __launch_bounds__(tile_width<T>() * TEAM)
+k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
+            const C2<T>* __restrict__ FB, long long fb_angle_stride,
+            long long fb_label_stride, int QB, int ha, int hb, int sh,
+            C2<T>* __restrict__ Z, long long z_angle_stride,
+            long long z_pair_stride, const C2<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
+  constexpr int TW = tile_width<T>();
+  const int t = blockIdx.x, a = blockIdx.y, beta = blockIdx.z;
+  const int team = threadIdx.x / TEAM;
+  const int lane = threadIdx.x % TEAM;
+  const int c = t * TW + team;
+  const C2<T>* fa_col = FA + a * fa_label_stride + (long long)c * P;
+  const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
+  C2<T>* z_base = Z + beta * z_angle_stride + (long long)t * sh * TW;
+  if constexpr (pair_cols_lds_twiddles<T, P>()) {
+    C2<T>* twl = smem + TW * lds_elems(P);
+    for (int x = threadIdx.x; x < P; x += blockDim.x) twl[x] = tw[x];
     __syncthreads();
-    {
-      const float4* s4 = reinterpret_cast<const float4*>(smem);
-      float4* d4 = reinterpret_cast<float4*>(z_base + (long long)(a * QB + b) * z_pair_stride);
-      for (int i = threadIdx.x; i < n16; i += blockDim.x) d4[i] = s4[i];
-    }
-    __syncthreads();
+    const FftTwTable<T, P, TEAM> ftw{twl};
+    pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, QB, a, ha, hb,
+                              sh, z_base, z_pair_stride, ftw, smem, c, team, lane);
+  } else {
+    FftTw<T, P, TEAM> ftw;
+    fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
+    pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, QB, a, ha, hb,
+                              sh, z_base, z_pair_stride, ftw, smem, c, team, lane);
   }
 }
 
@@ -89,7 +147,8 @@ template <typename T, int P>
 static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = col_team_for<T>(P);
   constexpr int TW = tile_width<T>();
-  const size_t shm = (size_t)TW * lds_elems(P) * sizeof(C2<T>);
+  const size_t shm = pair_cols_exch_bytes<T, P>() +
+                     (pair_cols_lds_twiddles<T, P>() ? (size_t)P * sizeof(C2<T>) : 0);
   auto fn = k_pair_cols<T, P, TEAM>;
   hipError_t e = hipFuncSetAttribute((const void*)fn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,

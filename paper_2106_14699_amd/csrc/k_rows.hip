@@ -39,18 +39,18 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-// Loads row i of pairs p0 (and p1 when has1) and builds the packed complex
-// sequence W(k) = Z_p0(k) + i Z_p1(k), k = lane + TEAM*q, from the two half
-// spectra (slot 0 carries k = 0 and k = P/2, both real).
+// Raw loads of row i of pairs p0 (and p1 when has1): element k of the half
+// spectrum that lane position k = lane + TEAM*q needs (its mirror P - k in
+// the upper half; slot 0 for k = 0 and k = P/2).
 template <typename T, int P, int TEAM>
-__device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
-                                          const C2<T>* __restrict__ z1,
-                                          bool has1, int tile_stride, int lane,
-                                          C2<T> (&w)[P / TEAM]) {
+__device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
+                                         const C2<T>* __restrict__ z1,
+                                         bool has1, int tile_stride, int lane,
+                                         C2<T> (&u0)[P / TEAM],
+                                         C2<T> (&u1)[P / TEAM]) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   constexpr int HALF = P / 2;
-  C2<T> u0[R], u1[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int k = lane + TEAM * q;
@@ -60,6 +60,16 @@ __device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
     u0[q] = z0[off];
     u1[q] = has1 ? z1[off] : mk<T>((T)0, (T)0);
   }
+}
+
+// Packed complex sequence W(k) = Z_p0(k) + i Z_p1(k) from the raw loads
+// (Hermitian extension of both half spectra).
+template <typename T, int P, int TEAM>
+__device__ __forceinline__ void build_pack(const C2<T> (&u0)[P / TEAM],
+                                           const C2<T> (&u1)[P / TEAM], int lane,
+                                           C2<T> (&w)[P / TEAM]) {
+  constexpr int R = P / TEAM;
+  constexpr int HALF = P / 2;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int k = lane + TEAM * q;
@@ -75,12 +85,23 @@ __device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
   }
 }
 
+template <typename T, int P, int TEAM>
+__device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
+                                          const C2<T>* __restrict__ z1,
+                                          bool has1, int tile_stride, int lane,
+                                          C2<T> (&w)[P / TEAM]) {
+  C2<T> u0[P / TEAM], u1[P / TEAM];
+  load_raw<T, P, TEAM>(z0, z1, has1, tile_stride, lane, u0, u1);
+  build_pack<T, P, TEAM>(u0, u1, lane, w);
+}
+
 template <typename T, int P, int TEAM, int BPW, int NTMAX>
 __global__ void __launch_bounds__(NTMAX)
 k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
-            int sw, int ph, const C2<T>* __restrict__ tw,
-            const double* __restrict__ logtab_g, double* __restrict__ mi_out,
+            int sw, int ph, int rpw, const C2<T>* __restrict__ tw,
+            const double* __restrict__ logtab_g,
+            const double* __restrict__ xlogtab_g, double* __restrict__ mi_out,
             long long mi_angle_stride, int32_t* __restrict__ n_out,
             long long n_angle_stride, uint32_t* __restrict__ maxn,
             uint32_t* __restrict__ flags, cmif_stats* __restrict__ stats) {
@@ -91,11 +112,11 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   const int NT = blockDim.x;
   C2<T>* exch = reinterpret_cast<C2<T>*>(smem_raw);
   double* ltab = reinterpret_cast<double*>(exch + (size_t)nteams * lds_elems(P));
-  double* sa_l = ltab + 512;                              // S_A per x
+  double* xlt = ltab + 512;                               // c log2 c, c < kXlogN
+  double* sa_l = xlt + kXlogN;                            // S_A per x
   uint32_t* n_l = reinterpret_cast<uint32_t*>(sa_l + P);  // N per x
   uint32_t* slot = n_l + P;                               // [2][P] C_a
 
-  const int i = blockIdx.x;     // map row
   const int beta = blockIdx.y;  // angle within batch
   const int tid = threadIdx.x;
   const int team = tid / TEAM;
@@ -103,111 +124,162 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   C2<T>* lds = exch + team * lds_elems(P);
 
   for (int x = tid; x < 512; x += NT) ltab[x] = logtab_g[x];
-  for (int x = tid; x < 2 * P; x += NT) slot[x] = 0u;
-  for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
+  for (int x = tid; x < kXlogN; x += NT) xlt[x] = xlogtab_g[x];
+  FftTw<T, P, TEAM> ftw;
+  fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
 
   const T scale = (T)1 / ((T)ph * (T)P);
-  const C2<T>* zrow = Z + beta * z_angle_stride + (long long)i * TW;
   const int tile_stride = sh * TW;
-
-  uint32_t cb[BPW][R];
-  double sab[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    sab[q] = 0.0;
-#pragma unroll
-    for (int bb = 0; bb < BPW; ++bb) cb[bb][q] = 0u;
-  }
-  float maxres = 0.0f;
-  __syncthreads();
-
   const int b_first = team * BPW;
   const int nq = QA * QB;
-  for (int a = 0; a < QA; ++a) {
-    uint32_t* sl = slot + (a & 1) * P;
-#pragma unroll
-    for (int pk = 0; pk < BPW / 2; ++pk) {
-      const int b0 = b_first + 2 * pk, b1 = b0 + 1;
-      const bool has0 = b0 < QB, has1 = b1 < QB;
-      C2<T> w[R];
-      if (has0) {
-        load_pack<T, P, TEAM>(zrow + (long long)(a * QB + b0) * z_pair_stride,
-                              zrow + (long long)(a * QB + b1) * z_pair_stride,
-                              has1, tile_stride, lane, w);
-      } else {
-#pragma unroll
-        for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
-      }
-      team_fft<T, P, TEAM, +1>(w, lds, tw, lane);
+  float maxres = 0.0f;
+  uint32_t nmax = 0u;
 
-      bool bad0 = false, bad1 = false;
+  const int i_end = min(sh, (int)(blockIdx.x + 1) * rpw);
+  for (int i = blockIdx.x * rpw; i < i_end; ++i) {
+    for (int x = tid; x < 2 * P; x += NT) slot[x] = 0u;
+    for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
+    __syncthreads();
+    const C2<T>* zrow = Z + beta * z_angle_stride + (long long)i * TW;
+
+    uint32_t cb[BPW][R];
+    double sab[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int x = lane + TEAM * q;
-        if (has0 && circ_to_map(x, P, wa, wb) >= 0) {
-          const T v0 = w[q].x * scale, v1 = w[q].y * scale;
-          const T r0 = round_half_even<T>(v0), r1 = round_half_even<T>(v1);
-          const float e0 = (float)fabs(v0 - r0), e1 = (float)fabs(v1 - r1);
-          bad0 |= e0 >= 0.25f;
-          bad1 |= e1 >= 0.25f;
-          maxres = fmaxf(maxres, fmaxf(e0, has1 ? e1 : 0.0f));
-          const uint32_t n0 = r0 > (T)0 ? (uint32_t)r0 : 0u;
-          const uint32_t n1 = r1 > (T)0 ? (uint32_t)r1 : 0u;
-          cb[2 * pk][q] += n0;
-          cb[2 * pk + 1][q] += n1;
-          sab[q] += xlog2x_u32(n0, ltab) + xlog2x_u32(n1, ltab);
-          if (n0 + n1 != 0u) atomicAdd(&sl[x], n0 + n1);
+    for (int q = 0; q < R; ++q) {
+      sab[q] = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < BPW; ++bb) cb[bb][q] = 0u;
+    }
+
+    // software pipeline: the raw loads of the next pack are in flight while
+    // the current pack is transformed and reduced
+    C2<T> nu0[R], nu1[R];
+    {
+      const int b0 = b_first, b1 = b0 + 1;
+      if (b0 < QB)
+        load_raw<T, P, TEAM>(zrow + (long long)b0 * z_pair_stride,
+                             zrow + (long long)b1 * z_pair_stride, b1 < QB,
+                             tile_stride, lane, nu0, nu1);
+    }
+    for (int a = 0; a < QA; ++a) {
+      uint32_t* sl = slot + (a & 1) * P;
+      uint32_t ca[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) ca[q] = 0u;
+#pragma unroll
+      for (int pk = 0; pk < BPW / 2; ++pk) {
+        const int b0 = b_first + 2 * pk, b1 = b0 + 1;
+        const bool has0 = b0 < QB, has1 = b1 < QB;
+        C2<T> w[R];
+        if (has0) {
+          build_pack<T, P, TEAM>(nu0, nu1, lane, w);
+        } else {
+#pragma unroll
+          for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
+        }
+        {
+          // next pack: (a, pk + 1), or (a + 1, 0)
+          const int na = pk + 1 < BPW / 2 ? a : a + 1;
+          const int nb0 = pk + 1 < BPW / 2 ? b0 + 2 : b_first;
+          if (na < QA && nb0 < QB)
+            load_raw<T, P, TEAM>(zrow + (long long)(na * QB + nb0) * z_pair_stride,
+                                 zrow + (long long)(na * QB + nb0 + 1) * z_pair_stride,
+                                 nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
+        }
+        team_fft<T, P, TEAM, +1>(w, lds, ftw, lane);
+
+        float e0max = 0.0f, e1max = 0.0f;
+        uint32_t big = 0u;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          if (circ_to_map(lane + TEAM * q, P, wa, wb) >= 0) {
+            const T v0 = w[q].x * scale, v1 = w[q].y * scale;
+            const T r0 = round_half_even<T>(v0), r1 = round_half_even<T>(v1);
+            e0max = fmaxf(e0max, (float)fabs(v0 - r0));
+            e1max = fmaxf(e1max, (float)fabs(v1 - r1));
+            const uint32_t n0 = (uint32_t)fmax(r0, (T)0);
+            const uint32_t n1 = (uint32_t)fmax(r1, (T)0);
+            cb[2 * pk][q] += n0;
+            cb[2 * pk + 1][q] += n1;
+            ca[q] += n0 + n1;
+            big |= n0 | n1;
+            sab[q] += xlt[min(n0, (uint32_t)(kXlogN - 1))] +
+                      xlt[min(n1, (uint32_t)(kXlogN - 1))];
+          }
+        }
+        if (big >= (uint32_t)kXlogN) {
+          // rare: counts beyond the table, replace the clamped entries
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            if (circ_to_map(lane + TEAM * q, P, wa, wb) >= 0) {
+              const uint32_t n0 = (uint32_t)fmax(round_half_even<T>(w[q].x * scale), (T)0);
+              const uint32_t n1 = (uint32_t)fmax(round_half_even<T>(w[q].y * scale), (T)0);
+              if (n0 >= (uint32_t)kXlogN)
+                sab[q] += xlog2x_u32(n0, ltab) - xlt[kXlogN - 1];
+              if (n1 >= (uint32_t)kXlogN)
+                sab[q] += xlog2x_u32(n1, ltab) - xlt[kXlogN - 1];
+            }
+          }
+        }
+        if (!has1) e1max = 0.0f;
+        maxres = fmaxf(maxres, fmaxf(e0max, e1max));
+        if (__ballot(has0 && e0max >= 0.25f) != 0ull && (tid % 64) == 0) {
+          const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b0], 1u);
+          if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+        }
+        if (__ballot(has1 && e1max >= 0.25f) != 0ull && (tid % 64) == 0) {
+          const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b1], 1u);
+          if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
         }
       }
-      if (__ballot(bad0 && has0) != 0ull && (tid % 64) == 0) {
-        const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b0], 1u);
-        if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
-      }
-      if (__ballot(bad1 && has1) != 0ull && (tid % 64) == 0) {
-        const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b1], 1u);
-        if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+      // exact C_a = sum over all teams' b of C_ab (integer atomics)
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (ca[q] != 0u) atomicAdd(&sl[lane + TEAM * q], ca[q]);
+      __syncthreads();
+      // C_a of this a is complete: fold it into S_A and N
+      for (int x = tid; x < P; x += NT) {
+        const uint32_t cv = sl[x];
+        if (cv != 0u) {
+          sl[x] = 0u;
+          sa_l[x] += cv < (uint32_t)kXlogN ? xlt[cv] : xlog2x_u32(cv, ltab);
+          n_l[x] += cv;
+        }
       }
     }
-    // C_a of this a is complete in LDS: fold it into S_A and N
+
+    // S_AB - S_B per team, then a fixed-order sum over teams
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double sb = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < BPW; ++bb) {
+        const uint32_t v = cb[bb][q];
+        sb += v < (uint32_t)kXlogN ? xlt[v] : xlog2x_u32(v, ltab);
+      }
+      sab[q] -= sb;
+    }
     __syncthreads();
+    double* part = reinterpret_cast<double*>(lds);
+#pragma unroll
+    for (int q = 0; q < R; ++q) part[lane + TEAM * q] = sab[q];
+    __syncthreads();
+
     for (int x = tid; x < P; x += NT) {
-      const uint32_t cv = sl[x];
-      if (cv != 0u) {
-        sl[x] = 0u;
-        sa_l[x] += xlog2x_u32(cv, ltab);
-        n_l[x] += cv;
+      const int j = circ_to_map(x, P, wa, wb);
+      if (j >= 0) {
+        double tsum = 0.0;
+        for (int g = 0; g < nteams; ++g)
+          tsum += reinterpret_cast<const double*>(exch + g * lds_elems(P))[x];
+        const uint32_t nn = n_l[x];
+        double mi = 0.0;
+        if (nn > 0u) mi = log2_u32(nn, ltab) + (tsum - sa_l[x]) / (double)nn;
+        if (mi_out) mi_out[beta * mi_angle_stride + (long long)i * sw + j] = mi;
+        if (n_out) n_out[beta * n_angle_stride + (long long)i * sw + j] = (int32_t)nn;
+        nmax = nn > nmax ? nn : nmax;
       }
     }
-  }
-
-  // S_AB - S_B per team, then a fixed-order sum over teams
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    double sb = 0.0;
-#pragma unroll
-    for (int bb = 0; bb < BPW; ++bb) sb += xlog2x_u32(cb[bb][q], ltab);
-    sab[q] -= sb;
-  }
-  __syncthreads();
-  double* part = reinterpret_cast<double*>(lds);
-#pragma unroll
-  for (int q = 0; q < R; ++q) part[lane + TEAM * q] = sab[q];
-  __syncthreads();
-
-  uint32_t nmax = 0u;
-  for (int x = tid; x < P; x += NT) {
-    const int j = circ_to_map(x, P, wa, wb);
-    if (j >= 0) {
-      double tsum = 0.0;
-      for (int g = 0; g < nteams; ++g)
-        tsum += reinterpret_cast<const double*>(exch + g * lds_elems(P))[x];
-      const uint32_t nn = n_l[x];
-      double mi = 0.0;
-      if (nn > 0u) mi = log2_u32(nn, ltab) + (tsum - sa_l[x]) / (double)nn;
-      if (mi_out) mi_out[beta * mi_angle_stride + (long long)i * sw + j] = mi;
-      if (n_out) n_out[beta * n_angle_stride + (long long)i * sw + j] = (int32_t)nn;
-      nmax = nn > nmax ? nn : nmax;
-    }
+    __syncthreads();  // part[] and the tables are reused by the next row
   }
   // wave max of N and of the residual, one atomic per wave
 #pragma unroll
@@ -248,6 +320,8 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
   const int nq = QA * QB;
   const int npk = (nq + 1) / 2;
   const int iters = (npk + nteams - 1) / nteams;
+  FftTw<T, P, TEAM> ftw;
+  fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
   for (int it = 0; it < iters; ++it) {
     const int pk = team + it * nteams;
     const int p0 = 2 * pk, p1 = p0 + 1;
@@ -261,7 +335,7 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
 #pragma unroll
       for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
     }
-    team_fft<T, P, TEAM, +1>(w, lds, tw, lane);
+    team_fft<T, P, TEAM, +1>(w, lds, ftw, lane);
     uint64_t d0 = 0, d1 = 0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -303,11 +377,13 @@ static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
   if (e != hipSuccess) return e;
-  dim3 grid(a.sh, a.nb);
+  const int rpw = a.rows_per_wg > 0 ? a.rows_per_wg : 1;
+  dim3 grid((a.sh + rpw - 1) / rpw, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
                      a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
-                     a.sh, a.sw, a.ph, a.tw, a.logtab, a.mi, a.mi_angle_stride,
-                     a.n, a.n_angle_stride, a.maxn, a.flags, a.stats);
+                     a.sh, a.sw, a.ph, rpw, a.tw, a.logtab, a.xlogtab, a.mi,
+                     a.mi_angle_stride, a.n, a.n_angle_stride, a.maxn, a.flags,
+                     a.stats);
   return hipGetLastError();
 }
 

@@ -50,6 +50,8 @@ struct PairRowsArgs {
   int QA, QB, ha, wa, hb, wb, sh, sw, ph, nb;
   const C2<T>* tw;       // P_w-entry table
   const double* logtab;  // 512 entries: log2(1 + j/256), 1/(1 + j/256)
+  const double* xlogtab; // kXlogN entries: c log2 c
+  int rows_per_wg;       // map rows handled by one workgroup
   double* mi;            // nullable, [nb][sh][sw]
   long long mi_angle_stride;
   int32_t* n;            // nullable, [nb][sh][sw]
@@ -100,8 +102,9 @@ struct PairRowsConfig {
 };
 
 inline size_t pair_rows_lds(size_t elem_real, int P, int nteams) {
-  return (size_t)nteams * lds_elems(P) * 2 * elem_real + 512 * sizeof(double) +
-         (size_t)P * sizeof(double) + 3 * (size_t)P * sizeof(uint32_t);
+  return (size_t)nteams * lds_elems(P) * 2 * elem_real +
+         (512 + kXlogN) * sizeof(double) + (size_t)P * sizeof(double) +
+         3 * (size_t)P * sizeof(uint32_t);
 }
 
 // false when no supported shape fits (LDS above 160 KiB or > 1024 lanes)
@@ -134,7 +137,7 @@ template <typename T>
 hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st);
 
 hipError_t launch_init_tables(void* tw32, void* tw64, int P, double* logtab,
-                              hipStream_t st);
+                              double* xlogtab, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
 hipError_t launch_check_labels(const uint8_t* lab, const uint8_t* msk,
                                long long n, int Q, cmif_stats* stats,
