@@ -77,8 +77,14 @@ typedef enum cmif_status {
 /* precision of the FFT stages (Sec. 3.2 "rounding ... to integers") */
 enum {
   CMIF_PREC_FP32_ROUNDED = 0, /* FP32 FFTs, counts rounded, residual check,
-                                 FP64 re-run of flagged label pairs */
-  CMIF_PREC_FP64 = 1          /* every FFT stage in FP64 */
+                                 FP64 re-run of flagged label pairs: each
+                                 pass of angles lists the (angle, a, b) whose
+                                 residual reached 0.25 (up to the plan's
+                                 fallback capacity, in angle-major pair
+                                 order), recomputes their joint counts from
+                                 FP64 spectra and reduces those angles
+                                 again with the exact counts */
+  CMIF_PREC_FP64 = 1          /* every FFT stage in FP64 (no re-run) */
 };
 
 enum {
@@ -87,7 +93,8 @@ enum {
 };
 
 enum {
-  /* send every label pair through the FP64 re-run, whatever its residual */
+  /* FP32_ROUNDED: list every label pair for the FP64 re-run, whatever its
+     residual (pairs beyond the capacity are counted as overflow) */
   CMIF_FLAG_FORCE_FALLBACK = 1u << 0,
   /* keep the schedule host-visible: one kernel per stage and angle, no
      graph capture (a debugging aid; results are identical) */
@@ -114,7 +121,9 @@ typedef struct cmif_plan_desc {
   uint32_t flags;            /* CMIF_FLAG_* */
   int32_t device;            /* HIP device ordinal */
   int32_t angle_batch;       /* angles per pipeline pass, 0 = automatic */
-  int32_t reserved;
+  int32_t fallback_capacity; /* FP32_ROUNDED: label pairs per pass that the
+                                FP64 re-run can take, 0 = min(64, pairs per
+                                pass), at most 4096; sizes scratch */
 } cmif_plan_desc;
 
 typedef struct cmif_plan_s* cmif_plan_t;

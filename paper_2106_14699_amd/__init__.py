@@ -59,7 +59,7 @@ class cmif_plan_desc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("device", ctypes.c_int32),
                 ("angle_batch", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("fallback_capacity", ctypes.c_int32)]
 
 
 class cmif_stats(ctypes.Structure):
@@ -244,7 +244,7 @@ class Plan:
                  q_b: int, angles: Sequence[float] | None = None,
                  gamma: float = 0.5, precision: str = "fp32",
                  mode: str = "hard", flags: int = 0, device: int = 0,
-                 angle_batch: int = 0):
+                 angle_batch: int = 0, fallback_capacity: int = 0):
         import torch
         self._torch = torch
         self.sizes = [tuple(int(v) for v in s) for s in sizes]
@@ -271,6 +271,7 @@ class Plan:
         d.flags = int(flags)
         d.device = self.device
         d.angle_batch = int(angle_batch)
+        d.fallback_capacity = int(fallback_capacity)
         self.handle = cmif_plan(d)
         self.persistent_bytes, self.scratch_bytes = cmif_workspace_size(
             self.handle)

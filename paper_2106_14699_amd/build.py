@@ -20,8 +20,15 @@ LIB = os.path.join(HERE, "libcmif.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "k_forward.hip", "k_pair.hip", "k_rows.hip",
-           "k_misc.hip"]
+# (source, object name, defines): the row kernels are compiled once per
+# (precision, FFT length) so that the build runs in parallel
+SOURCES = [("api.cpp", "api", []), ("k_forward.hip", "k_forward", []),
+           ("k_pair.hip", "k_pair", []), ("k_misc.hip", "k_misc", []),
+           ("k_rows.hip", "k_rows", [])]
+for _t, _tn in (("float", "f32"), ("double", "f64")):
+    for _p in (128, 256, 512, 1024, 2048):
+        SOURCES.append(("k_rows.hip", f"k_rows_{_tn}_{_p}",
+                        [f"-DCMIF_ROWS_T={_t}", f"-DCMIF_ROWS_P={_p}"]))
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -32,9 +39,10 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(entry) -> str:
+    src, name, defines = entry
+    obj = os.path.join(OUT_DIR, name + ".o")
+    cmd = [HIPCC, *FLAGS, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-xhip")
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,8 +54,11 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
+    # largest objects first
+    order = sorted(SOURCES, key=lambda e: (e[0] != "k_rows.hip" or not e[2],
+                                           -len(e[1])))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(_compile, order))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
            *objs]

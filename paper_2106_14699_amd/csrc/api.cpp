@@ -10,6 +10,10 @@
 //     pair columns   conj(F_A,a) F_B,b and inverse FFT along y -> Z
 //     pair rows      inverse FFT along x, rounding, residual check, fused
 //                    entropy sums -> MI map, N map, max N, flags
+//     FP64 re-run    (FP32 plans) list of flagged pairs -> gated FP64
+//                    forward transforms, pair columns and counts of the
+//                    listed pairs -> pair rows again for the gated angles,
+//                    the listed pairs entering with exact counts
 //     argmax         gamma-eligible argmax per angle, running best (Alg. 1)
 #include <hip/hip_runtime.h>
 
@@ -46,16 +50,21 @@ struct PairPlan {
 };
 
 struct ScratchLayout {
-  size_t xa, fa, xb, fb, z, mi, n, maxn, flags, partial, running, stats, end;
+  size_t xa, fa, xb, fb, z, mi, n, maxn, flags, partial, running, stats;
+  // FP64 re-run (FP32 plans only)
+  size_t xa64, fa64, xb64, fb64, z64, cnt64, items, n_items, ovr, gate;
+  size_t end;
 };
 
 enum Stage {
   ST_CHECK, ST_FWD_ROWS, ST_FWD_COLS, ST_PAIR_COLS, ST_PAIR_ROWS,
-  ST_PAIR_COUNTS, ST_ARGMAX, ST_FILL, ST_TABLES, ST_COUNT
+  ST_PAIR_COUNTS, ST_ARGMAX, ST_FILL, ST_TABLES, ST_FB_LIST, ST_FB_FWD,
+  ST_FB_PAIR, ST_FB_ROWS, ST_COUNT
 };
 const char* const kStageNames[ST_COUNT] = {
     "check_labels", "fwd_rows", "fwd_cols", "pair_cols", "pair_rows",
-    "pair_counts", "argmax", "fill", "tables"};
+    "pair_counts", "argmax", "fill", "tables", "fb_list", "fb_forward",
+    "fb_pairs", "fb_rows"};
 
 struct ProfRec {
   int stage;
@@ -89,6 +98,7 @@ struct cmif_plan_s {
   std::vector<double> angles;
   std::vector<int32_t> rc, rs;
   int batch = 1;
+  int fb_cap = 0;               // FP64 re-run items per pass (FP32 plans)
   std::vector<int> plens;       // distinct FFT lengths
   std::vector<size_t> tw_off;   // per plens entry: FP32 table, FP64 follows
   size_t logtab_off = 0;
@@ -129,6 +139,19 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
   L.partial = take(nb * nchunks * sizeof(ArgPartial));
   L.running = take(sizeof(cmif_best));
   L.stats = take(sizeof(cmif_stats));
+  if (P.fb_cap > 0) {
+    const size_t E64 = sizeof(double2), cap = P.fb_cap;
+    L.xa64 = take(qa * half * g.ha * E64);
+    L.fa64 = take(qa * half * g.ph * E64);
+    L.xb64 = take(nb * qb * half * g.hb * E64);
+    L.fb64 = take(nb * qb * half * g.ph * E64);
+    L.z64 = take(cap * half * g.sh * E64);
+    L.cnt64 = take(cap * (size_t)g.sh * g.sw * sizeof(int32_t));
+    L.items = take(cap * sizeof(int4));
+    L.n_items = take(sizeof(uint32_t));
+    L.ovr = take(nb * qa * qb * sizeof(int32_t));
+    L.gate = take((nb + 1) * sizeof(uint32_t));
+  }
   L.end = o;
   return L;
 }
@@ -219,6 +242,42 @@ struct CallOutputs {
 };
 
 template <typename T>
+const C2<T>* twiddles(const cmif_plan_s& P, const uint8_t* pers, int len) {
+  const size_t off = P.tw_off[find_plen(P, len)] +
+                     (sizeof(T) == 8 ? (size_t)len * sizeof(float2) : 0);
+  return reinterpret_cast<const C2<T>*>(pers + off);
+}
+
+// Forward transforms of the level sets of one image for `nb` angles
+// (rotation r[b]); gate (nullable) skips angles with gate[b] == 0.
+template <typename T>
+cmif_status forward(cmif_plan_s& P, hipStream_t st, int stage_rows,
+                     int stage_cols, const uint8_t* lab, const uint8_t* msk,
+                     int H, int W, int Q, int nb, const int32_t* rc,
+                     const int32_t* rs, const PairPlan& g, const uint8_t* pers,
+                     C2<T>* x, C2<T>* f, const uint32_t* gate) {
+  using CT = C2<T>;
+  const int half = g.pw / 2;
+  FwdRowsArgs<T> r{};
+  r.lab = lab; r.msk = msk; r.H = H; r.W = W; r.Q = Q; r.nb = nb;
+  for (int b = 0; b < nb; ++b) { r.rot.c[b] = rc[b]; r.rot.s[b] = rs[b]; }
+  r.xrow = x; r.angle_stride = (long long)Q * half * H;
+  r.tw = twiddles<T>(P, pers, g.pw); r.gate = gate;
+  STAGE(stage_rows, nb * (2.0 * H * W + (double)Q * half * H * sizeof(CT)),
+        launch_fwd_rows<T>(g.pw, r, st));
+  FwdColsArgs<T> c{};
+  c.xrow = x; c.H = H; c.tiles = half / tile_width<T>(); c.Q = Q; c.nb = nb;
+  c.x_angle_stride = (long long)Q * half * H;
+  c.x_label_stride = (long long)half * H;
+  c.F = f; c.f_angle_stride = (long long)Q * half * g.ph;
+  c.f_label_stride = (long long)half * g.ph; c.tw = twiddles<T>(P, pers, g.ph);
+  c.gate = gate;
+  STAGE(stage_cols, nb * (double)Q * half * (H + g.ph) * sizeof(CT),
+        launch_fwd_cols<T>(g.ph, c, st));
+  return CMIF_OK;
+}
+
+template <typename T>
 cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
                      const uint8_t* ma, const uint8_t* lb, const uint8_t* mb,
                      const CallOutputs& o, uint8_t* pers, uint8_t* scr,
@@ -259,20 +318,11 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
   }
 
   // forward transforms of A's level sets (identity resampling)
+  const int32_t id_c = 65536, id_s = 0;
   {
-    FwdRowsArgs<T> a{};
-    a.lab = la; a.msk = ma; a.H = g.ha; a.W = g.wa; a.Q = qa; a.nb = 1;
-    a.rot.c[0] = 65536; a.rot.s[0] = 0;
-    a.xrow = xa; a.angle_stride = 0; a.tw = tw_w;
-    STAGE(ST_FWD_ROWS, 2.0 * g.ha * g.wa + (double)qa * half * g.ha * sizeof(CT),
-          launch_fwd_rows<T>(g.pw, a, st));
-    FwdColsArgs<T> c{};
-    c.xrow = xa; c.H = g.ha; c.tiles = tiles; c.Q = qa; c.nb = 1;
-    c.x_angle_stride = 0; c.x_label_stride = (long long)half * g.ha;
-    c.F = fa; c.f_angle_stride = 0; c.f_label_stride = (long long)half * g.ph;
-    c.tw = tw_h;
-    STAGE(ST_FWD_COLS, (double)qa * half * (g.ha + g.ph) * sizeof(CT),
-          launch_fwd_cols<T>(g.ph, c, st));
+    cmif_status s = forward<T>(P, st, ST_FWD_ROWS, ST_FWD_COLS, la, ma, g.ha,
+                               g.wa, qa, 1, &id_c, &id_s, g, pers, xa, fa, nullptr);
+    if (s != CMIF_OK) return s;
   }
   const int nang = (int)P.angles.size();
   const long long map_stride = (long long)g.sh * g.sw;
@@ -281,20 +331,12 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
   const bool want_best = o.best != nullptr || o.per_angle != nullptr;
   for (int a0 = 0; a0 < nang; a0 += P.batch) {
     const int nb = std::min(P.batch, nang - a0);
-    FwdRowsArgs<T> r{};
-    r.lab = lb; r.msk = mb; r.H = g.hb; r.W = g.wb; r.Q = qb; r.nb = nb;
-    for (int b = 0; b < nb; ++b) { r.rot.c[b] = P.rc[a0 + b]; r.rot.s[b] = P.rs[a0 + b]; }
-    r.xrow = xb; r.angle_stride = (long long)qb * half * g.hb; r.tw = tw_w;
-    STAGE(ST_FWD_ROWS, nb * (2.0 * g.hb * g.wb + (double)qb * half * g.hb * sizeof(CT)),
-          launch_fwd_rows<T>(g.pw, r, st));
-    FwdColsArgs<T> c{};
-    c.xrow = xb; c.H = g.hb; c.tiles = tiles; c.Q = qb; c.nb = nb;
-    c.x_angle_stride = (long long)qb * half * g.hb;
-    c.x_label_stride = (long long)half * g.hb;
-    c.F = fb; c.f_angle_stride = (long long)qb * half * g.ph;
-    c.f_label_stride = (long long)half * g.ph; c.tw = tw_h;
-    STAGE(ST_FWD_COLS, nb * (double)qb * half * (g.hb + g.ph) * sizeof(CT),
-          launch_fwd_cols<T>(g.ph, c, st));
+    {
+      cmif_status s = forward<T>(P, st, ST_FWD_ROWS, ST_FWD_COLS, lb, mb, g.hb,
+                                 g.wb, qb, nb, &P.rc[a0], &P.rs[a0], g, pers, xb,
+                                 fb, nullptr);
+      if (s != CMIF_OK) return s;
+    }
 
     STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(maxn, 0u, nb, st));
     STAGE(ST_FILL, 4.0 * nb * qa * qb,
@@ -339,6 +381,63 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
       STAGE(ST_PAIR_COUNTS,
             nb * (double)qa * qb * (half * g.sh * sizeof(CT) + (o.counts ? 4.0 * g.sh * g.sw : 0.0)),
             launch_pair_counts<T>(g.pw, pk, st));
+    }
+
+    if (!fp64 && P.fb_cap > 0) {
+      // FP64 re-run of the flagged pairs (everything stays on the device:
+      // the list decides, the gates skip, nothing returns to the host)
+      using C64 = C2<double>;
+      C64* xa64 = reinterpret_cast<C64*>(scr + L.xa64);
+      C64* fa64 = reinterpret_cast<C64*>(scr + L.fa64);
+      C64* xb64 = reinterpret_cast<C64*>(scr + L.xb64);
+      C64* fb64 = reinterpret_cast<C64*>(scr + L.fb64);
+      C64* z64 = reinterpret_cast<C64*>(scr + L.z64);
+      int32_t* cnt64 = reinterpret_cast<int32_t*>(scr + L.cnt64);
+      int4* items = reinterpret_cast<int4*>(scr + L.items);
+      uint32_t* n_items = reinterpret_cast<uint32_t*>(scr + L.n_items);
+      int32_t* ovr = reinterpret_cast<int32_t*>(scr + L.ovr);
+      uint32_t* gate = reinterpret_cast<uint32_t*>(scr + L.gate);
+      uint64_t* dig = o.digest ? o.digest + (long long)a0 * qa * qb : nullptr;
+      FbListArgs fl{};
+      fl.flags = flags; fl.nb = nb; fl.QA = qa; fl.QB = qb;
+      fl.force = (P.d.flags & CMIF_FLAG_FORCE_FALLBACK) ? 1 : 0;
+      fl.capacity = P.fb_cap; fl.items = items; fl.n_items = n_items;
+      fl.ovr = ovr; fl.gate = gate; fl.maxn = maxn; fl.digest = dig;
+      fl.stats = stats;
+      STAGE(ST_FB_LIST, 4.0 * nb * qa * qb * 2, launch_fb_list(fl, st));
+      cmif_status s = forward<double>(P, st, ST_FB_FWD, ST_FB_FWD, la, ma, g.ha,
+                                      g.wa, qa, 1, &id_c, &id_s, g, pers, xa64,
+                                      fa64, gate + nb);
+      if (s != CMIF_OK) return s;
+      s = forward<double>(P, st, ST_FB_FWD, ST_FB_FWD, lb, mb, g.hb, g.wb, qb, nb,
+                          &P.rc[a0], &P.rs[a0], g, pers, xb64, fb64, gate);
+      if (s != CMIF_OK) return s;
+      const int tiles64 = half / tile_width<double>();
+      PairColsArgs<double> qc{};
+      qc.FA = fa64; qc.fa_label_stride = (long long)half * g.ph;
+      qc.FB = fb64; qc.fb_angle_stride = (long long)qb * half * g.ph;
+      qc.fb_label_stride = (long long)half * g.ph;
+      qc.QA = qa; qc.QB = qb; qc.ha = g.ha; qc.hb = g.hb; qc.sh = g.sh;
+      qc.tiles = tiles64; qc.nb = nb; qc.Z = z64; qc.z_angle_stride = 0;
+      qc.z_pair_stride = (long long)half * g.sh;
+      qc.tw = twiddles<double>(P, pers, g.ph);
+      qc.items = items; qc.n_items = n_items; qc.max_items = P.fb_cap;
+      STAGE(ST_FB_PAIR, 0.0, launch_pair_cols<double>(g.ph, qc, st));
+      PairCountsArgs<double> qk{};
+      qk.Z = z64; qk.z_angle_stride = 0; qk.z_pair_stride = qc.z_pair_stride;
+      qk.QA = qa; qk.QB = qb; qk.wa = g.wa; qk.wb = g.wb; qk.sh = g.sh;
+      qk.sw = g.sw; qk.ph = g.ph; qk.nb = 1;
+      qk.tw = twiddles<double>(P, pers, g.pw);
+      qk.counts = o.counts ? o.counts + (long long)a0 * qa * qb * map_stride : nullptr;
+      qk.counts_angle_stride = (long long)qa * qb * map_stride;
+      qk.digest = dig; qk.items = items; qk.n_items = n_items;
+      qk.item_counts = cnt64;
+      STAGE(ST_FB_PAIR, 0.0, launch_pair_counts<double>(g.pw, qk, st));
+      PairRowsArgs<T> rr = pr;
+      rr.flags = nullptr;
+      rr.stats = nullptr;
+      rr.gate = gate; rr.ovr = ovr; rr.ovc = cnt64;
+      STAGE(ST_FB_ROWS, 0.0, launch_pair_rows<T>(g.pw, rr, st));
     }
 
     if (want_best) {
@@ -523,6 +622,8 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
                 "angles_rad may be NULL only with n_angles = 1");
   if (d->angle_batch < 0)
     return fail(CMIF_ERR_INVALID_ARGUMENT, "angle_batch must be >= 0");
+  if (d->fallback_capacity < 0 || d->fallback_capacity > 4096)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "fallback_capacity must be in [0, 4096]");
   if (d->mode == CMIF_MODE_SOFT)
     return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
 
@@ -583,6 +684,11 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   batch = std::min(batch, kMaxBatch);
   batch = std::min(batch, d->n_angles);
   P->batch = std::max(batch, 1);
+  if (d->precision == CMIF_PREC_FP32_ROUNDED) {
+    const int per_pass = P->batch * d->q_a * d->q_b;
+    const int cap = d->fallback_capacity > 0 ? d->fallback_capacity : 64;
+    P->fb_cap = std::min(cap, per_pass);
+  }
   // persistent: per FFT length FP32 + FP64 twiddles, then the log table
   size_t o = 0;
   for (int len : P->plens) {

@@ -27,13 +27,15 @@ template <typename T, int P, int TEAM>
 __global__ void __launch_bounds__(4 * TEAM)
 k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
            int H, int W, int Q, RotArgs rot, C2<T>* __restrict__ xrow,
-           long long angle_stride, const C2<T>* __restrict__ tw) {
+           long long angle_stride, const C2<T>* __restrict__ tw,
+           const uint32_t* __restrict__ gate) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   const int y = blockIdx.x;
   const int beta = blockIdx.y;
+  if (gate != nullptr && gate[beta] == 0u) return;  // nothing to redo here
   const int nteams = blockDim.x / TEAM;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
@@ -115,12 +117,13 @@ __global__ void __launch_bounds__(tile_width<T>() * TEAM)
 k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
            long long x_label_stride, C2<T>* __restrict__ F,
            long long f_angle_stride, long long f_label_stride,
-           const C2<T>* __restrict__ tw) {
+           const C2<T>* __restrict__ tw, const uint32_t* __restrict__ gate) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   const int t = blockIdx.x, lbl = blockIdx.y, beta = blockIdx.z;
+  if (gate != nullptr && gate[beta] == 0u) return;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
   const C2<T>* src = xrow + beta * x_angle_stride + lbl * x_label_stride +
@@ -173,7 +176,7 @@ static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
   if (e != hipSuccess) return e;
   dim3 grid(a.H, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.lab, a.msk, a.H,
-                     a.W, a.Q, a.rot, a.xrow, a.angle_stride, a.tw);
+                     a.W, a.Q, a.rot, a.xrow, a.angle_stride, a.tw, a.gate);
   return hipGetLastError();
 }
 
@@ -202,7 +205,7 @@ static hipError_t launch_cols_p(const FwdColsArgs<T>& a, hipStream_t st) {
   dim3 grid(a.tiles, a.Q, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.xrow, a.H,
                      a.x_angle_stride, a.x_label_stride, a.F, a.f_angle_stride,
-                     a.f_label_stride, a.tw);
+                     a.f_label_stride, a.tw, a.gate);
   return hipGetLastError();
 }
 

@@ -131,6 +131,80 @@ k_argmax_partial(const double* __restrict__ mi, const int32_t* __restrict__ nmap
   }
 }
 
+// FP64 re-run list (Sec. 3.2: a transform whose rounding residual is too
+// large is recomputed in double precision).  One workgroup walks the batch's
+// (angle, pair) flags in order and keeps the first `capacity` flagged ones:
+// items[s] = (angle, a, b), ovr[angle][pair] = s (else -1), gate[angle] = 1
+// for angles with an item and gate[nb] = 1 if there is any.  The gated
+// angles' max-N is cleared (their rows are reduced again) and so are the
+// digests of listed pairs (their exact counts are emitted again).
+__global__ void __launch_bounds__(1024)
+k_fb_list(const uint32_t* __restrict__ flags, int nb, int QA, int QB, int force,
+          int capacity, int4* __restrict__ items, uint32_t* __restrict__ n_items,
+          int32_t* __restrict__ ovr, uint32_t* __restrict__ gate,
+          uint32_t* __restrict__ maxn, uint64_t* __restrict__ digest,
+          cmif_stats* __restrict__ stats) {
+  __shared__ uint32_t wave_cnt[16];
+  __shared__ uint32_t gate_l[kMaxBatch];
+  const int tid = threadIdx.x, wave = tid / 64, wl = tid % 64;
+  const int nwaves = blockDim.x / 64;
+  const int nq = QA * QB;
+  const int total = nb * nq;
+  for (int b = tid; b < kMaxBatch; b += blockDim.x) gate_l[b] = 0u;
+  __syncthreads();
+  uint32_t base = 0;  // flagged items before this chunk (uniform)
+  for (int c0 = 0; c0 < total; c0 += blockDim.x) {
+    const int idx = c0 + tid;
+    const bool f = idx < total && (force != 0 || flags[idx] != 0u);
+    const uint64_t bal = __ballot(f);
+    const uint32_t below = (uint32_t)__popcll(bal & ((1ull << wl) - 1ull));
+    if (wl == 0) wave_cnt[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, chunk = 0;
+    for (int w = 0; w < nwaves; ++w) {
+      if (w < wave) before += wave_cnt[w];
+      chunk += wave_cnt[w];
+    }
+    if (idx < total) {
+      int32_t slot = -1;
+      const uint32_t pos = base + before + below;
+      if (f && pos < (uint32_t)capacity) {
+        const int beta = idx / nq, pr = idx % nq;
+        items[pos] = make_int4(beta, pr / QB, pr % QB, 0);
+        slot = (int32_t)pos;
+        gate_l[beta] = 1u;
+        if (digest) digest[idx] = 0ull;
+      }
+      ovr[idx] = slot;
+    }
+    base += chunk;
+    __syncthreads();  // wave_cnt is rewritten by the next chunk
+  }
+  const uint32_t kept = base < (uint32_t)capacity ? base : (uint32_t)capacity;
+  uint32_t any = 0u;
+  for (int b = 0; b < nb; ++b) any |= gate_l[b];
+  for (int b = tid; b < nb; b += blockDim.x) {
+    gate[b] = gate_l[b];
+    if (gate_l[b]) maxn[b] = 0u;
+  }
+  if (tid == 0) {
+    gate[nb] = any;
+    *n_items = kept;
+    if (stats) {
+      atomicAdd(&stats->fallback_pairs, kept);
+      atomicAdd(&stats->fallback_overflow, base - kept);
+    }
+  }
+}
+
+hipError_t launch_fb_list(const FbListArgs& a, hipStream_t st) {
+  if (a.nb < 1 || a.nb > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fb_list, dim3(1), dim3(1024), 0, st, a.flags, a.nb, a.QA,
+                     a.QB, a.force, a.capacity, a.items, a.n_items, a.ovr,
+                     a.gate, a.maxn, a.digest, a.stats);
+  return hipGetLastError();
+}
+
 hipError_t launch_argmax(const ArgmaxArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_argmax_partial, dim3(a.nchunks, a.nb), dim3(256), 0, st,
                      a.mi, a.n, a.angle_stride, a.maxn, a.sh, a.sw,

@@ -59,12 +59,14 @@ __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* sme
   __syncthreads();
 }
 
+// Runs labels b in [b_begin, b_end) of B against label a of A; output pair
+// slot of b is zpair0 + (b - b_begin).
 template <typename T, int P, int TEAM, class TWS>
 __device__ __forceinline__ void pair_cols_run(
     const C2<T>* __restrict__ fa_col, const C2<T>* __restrict__ fb_base,
-    long long fb_label_stride, int QB, int a, int ha, int hb, int sh,
-    C2<T>* __restrict__ z_base, long long z_pair_stride, const TWS& ftw,
-    C2<T>* smem, int c, int team, int lane) {
+    long long fb_label_stride, int b_begin, int b_end, int zpair0, int ha,
+    int hb, int sh, C2<T>* __restrict__ z_base, long long z_pair_stride,
+    const TWS& ftw, C2<T>* smem, int c, int team, int lane) {
   constexpr int R = P / TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
   C2<T> fa[R];
@@ -73,24 +75,28 @@ __device__ __forceinline__ void pair_cols_run(
   if (c != 0) {
     // software pipeline: the next b's column is in flight during this FFT
     C2<T> fbn[R];
+    {
+      const C2<T>* fb0 = fb_base + b_begin * fb_label_stride;
 #pragma unroll
-    for (int q = 0; q < R; ++q) fbn[q] = fb_base[lane + TEAM * q];
-    for (int b = 0; b < QB; ++b) {
+      for (int q = 0; q < R; ++q) fbn[q] = fb0[lane + TEAM * q];
+    }
+    for (int b = b_begin; b < b_end; ++b) {
       C2<T> v[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) v[q] = cmulc<T>(fa[q], fbn[q]);
-      if (b + 1 < QB) {
+      if (b + 1 < b_end) {
         const C2<T>* fb_next = fb_base + (b + 1) * fb_label_stride;
 #pragma unroll
         for (int q = 0; q < R; ++q) fbn[q] = fb_next[lane + TEAM * q];
       }
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
-      pair_cols_store<T, P, TEAM>(v, smem, z_base + (long long)(a * QB + b) * z_pair_stride,
-                                  ha, hb, sh, team, lane);
+      pair_cols_store<T, P, TEAM>(
+          v, smem, z_base + (long long)(zpair0 + b - b_begin) * z_pair_stride, ha,
+          hb, sh, team, lane);
     }
   } else {
     // slot 0 packs the k_x = 0 and k_x = P_w/2 columns (both Hermitian)
-    for (int b = 0; b < QB; ++b) {
+    for (int b = b_begin; b < b_end; ++b) {
       const C2<T>* fb_col = fb_base + b * fb_label_stride;
       C2<T> v[R];
 #pragma unroll
@@ -105,8 +111,9 @@ __device__ __forceinline__ void pair_cols_run(
         v[q] = mk<T>(y0.x - y1.y, y0.y + y1.x);  // y0 + i y1
       }
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
-      pair_cols_store<T, P, TEAM>(v, smem, z_base + (long long)(a * QB + b) * z_pair_stride,
-                                  ha, hb, sh, team, lane);
+      pair_cols_store<T, P, TEAM>(
+          v, smem, z_base + (long long)(zpair0 + b - b_begin) * z_pair_stride, ha,
+          hb, sh, team, lane);
     }
   }
 }
@@ -117,29 +124,54 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
             const C2<T>* __restrict__ FB, long long fb_angle_stride,
             long long fb_label_stride, int QB, int ha, int hb, int sh,
             C2<T>* __restrict__ Z, long long z_angle_stride,
-            long long z_pair_stride, const C2<T>* __restrict__ tw) {
+            long long z_pair_stride, const C2<T>* __restrict__ tw,
+            const int4* __restrict__ items, const uint32_t* __restrict__ n_items) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int TW = tile_width<T>();
-  const int t = blockIdx.x, a = blockIdx.y, beta = blockIdx.z;
+  const int t = blockIdx.x;
+  int a, beta, b_begin, b_end, zpair0;
+  C2<T>* z_base;
+  if (items == nullptr) {
+    // all pairs: workgroup (tile, a, angle) runs every b
+    a = blockIdx.y;
+    beta = blockIdx.z;
+    b_begin = 0;
+    b_end = QB;
+    zpair0 = a * QB;
+    z_base = Z + beta * z_angle_stride + (long long)t * sh * TW;
+  } else {
+    // item list: workgroup (tile, item) runs one pair (angle, a, b) of the
+    // list into slot `item` of Z
+    const int it = blockIdx.y;
+    if ((uint32_t)it >= *n_items) return;
+    const int4 e = items[it];
+    beta = e.x;
+    a = e.y;
+    b_begin = e.z;
+    b_end = e.z + 1;
+    zpair0 = it;
+    z_base = Z + (long long)t * sh * TW;
+  }
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
   const int c = t * TW + team;
   const C2<T>* fa_col = FA + a * fa_label_stride + (long long)c * P;
   const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
-  C2<T>* z_base = Z + beta * z_angle_stride + (long long)t * sh * TW;
   if constexpr (pair_cols_lds_twiddles<T, P>()) {
     C2<T>* twl = smem + TW * lds_elems(P);
     for (int x = threadIdx.x; x < P; x += blockDim.x) twl[x] = tw[x];
     __syncthreads();
     const FftTwTable<T, P, TEAM> ftw{twl};
-    pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, QB, a, ha, hb,
-                              sh, z_base, z_pair_stride, ftw, smem, c, team, lane);
+    pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, b_begin, b_end,
+                              zpair0, ha, hb, sh, z_base, z_pair_stride, ftw,
+                              smem, c, team, lane);
   } else {
     FftTw<T, P, TEAM> ftw;
     fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
-    pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, QB, a, ha, hb,
-                              sh, z_base, z_pair_stride, ftw, smem, c, team, lane);
+    pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, b_begin, b_end,
+                              zpair0, ha, hb, sh, z_base, z_pair_stride, ftw,
+                              smem, c, team, lane);
   }
 }
 
@@ -154,10 +186,11 @@ static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
   if (e != hipSuccess) return e;
-  dim3 grid(a.tiles, a.QA, a.nb);
+  dim3 grid = a.items ? dim3(a.tiles, a.max_items, 1) : dim3(a.tiles, a.QA, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.FA, a.fa_label_stride,
                      a.FB, a.fb_angle_stride, a.fb_label_stride, a.QB, a.ha,
-                     a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw);
+                     a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw,
+                     a.items, a.n_items);
   return hipGetLastError();
 }
 

@@ -104,9 +104,12 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             const double* __restrict__ xlogtab_g, double* __restrict__ mi_out,
             long long mi_angle_stride, int32_t* __restrict__ n_out,
             long long n_angle_stride, uint32_t* __restrict__ maxn,
-            uint32_t* __restrict__ flags, cmif_stats* __restrict__ stats) {
+            uint32_t* __restrict__ flags, cmif_stats* __restrict__ stats,
+            const uint32_t* __restrict__ gate, const int32_t* __restrict__ ovr,
+            const int32_t* __restrict__ ovc) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
+  if (gate != nullptr && gate[blockIdx.y] == 0u) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nteams = blockDim.x / TEAM;
   const int NT = blockDim.x;
@@ -187,6 +190,25 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
                                  nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
         }
         team_fft<T, P, TEAM, +1>(w, lds, ftw, lane);
+        if (ovr != nullptr) {
+          // re-run: pairs recomputed in FP64 enter with their exact counts
+          // (count * P_h P_w is exact, so the rounding below returns it)
+          const int o0 = has0 ? ovr[beta * nq + a * QB + b0] : -1;
+          const int o1 = has1 ? ovr[beta * nq + a * QB + b1] : -1;
+          if (o0 >= 0 || o1 >= 0) {
+            const T unscale = (T)ph * (T)P;
+            const long long mrow = (long long)i * sw;
+            const long long mstride = (long long)sh * sw;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              const int j = circ_to_map(lane + TEAM * q, P, wa, wb);
+              if (j >= 0) {
+                if (o0 >= 0) w[q].x = (T)ovc[o0 * mstride + mrow + j] * unscale;
+                if (o1 >= 0) w[q].y = (T)ovc[o1 * mstride + mrow + j] * unscale;
+              }
+            }
+          }
+        }
 
         float e0max = 0.0f, e1max = 0.0f;
         uint32_t big = 0u;
@@ -223,13 +245,15 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         }
         if (!has1) e1max = 0.0f;
         maxres = fmaxf(maxres, fmaxf(e0max, e1max));
-        if (__ballot(has0 && e0max >= 0.25f) != 0ull && (tid % 64) == 0) {
-          const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b0], 1u);
-          if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
-        }
-        if (__ballot(has1 && e1max >= 0.25f) != 0ull && (tid % 64) == 0) {
-          const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b1], 1u);
-          if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+        if (flags != nullptr) {
+          if (__ballot(has0 && e0max >= 0.25f) != 0ull && (tid % 64) == 0) {
+            const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b0], 1u);
+            if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+          }
+          if (__ballot(has1 && e1max >= 0.25f) != 0ull && (tid % 64) == 0) {
+            const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b1], 1u);
+            if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
+          }
         }
       }
       // exact C_a = sum over all teams' b of C_ab (integer atomics)
@@ -299,14 +323,17 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 // Count emission: workgroup (map row, angle); each team takes label pairs
 // two at a time (a-major order) and writes rint(count) to
 // counts[beta][pair][i][j] and/or adds sum_j count * splitmix64(i*S_w + j)
-// into digest[beta][pair] (64-bit wrap-around, order-free).
+// into digest[beta][pair] (64-bit wrap-around, order-free).  In item mode
+// the slots of Z are list items (angle, a, b) and the grid has one angle.
 template <typename T, int P, int TEAM>
 __global__ void __launch_bounds__(4 * TEAM)
 k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
               long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
               int sw, int ph, const C2<T>* __restrict__ tw,
               int32_t* __restrict__ counts, long long counts_angle_stride,
-              uint64_t* __restrict__ digest) {
+              uint64_t* __restrict__ digest, const int4* __restrict__ items,
+              const uint32_t* __restrict__ n_items,
+              int32_t* __restrict__ item_counts) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -317,7 +344,9 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
   C2<T>* lds = exch + team * lds_elems(P);
   const T scale = (T)1 / ((T)ph * (T)P);
   const C2<T>* zrow = Z + beta * z_angle_stride + (long long)i * TW;
-  const int nq = QA * QB;
+  const int npairs = QA * QB;
+  const int nq = items ? (int)*n_items : npairs;  // slots of Z to emit
+  if (nq == 0) return;
   const int npk = (nq + 1) / 2;
   const int iters = (npk + nteams - 1) / nteams;
   FftTw<T, P, TEAM> ftw;
@@ -336,6 +365,14 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
       for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
     }
     team_fft<T, P, TEAM, +1>(w, lds, ftw, lane);
+    // output angle and pair of slots p0, p1
+    int g0 = beta, t0 = p0, g1 = beta, t1 = p1;
+    if (items != nullptr) {
+      if (has0) { const int4 e = items[p0]; g0 = e.x; t0 = e.y * QB + e.z; }
+      if (has1) { const int4 e = items[p1]; g1 = e.x; t1 = e.y * QB + e.z; }
+    }
+    int32_t* cbase0 = counts ? counts + g0 * counts_angle_stride : nullptr;
+    int32_t* cbase1 = counts ? counts + g1 * counts_angle_stride : nullptr;
     uint64_t d0 = 0, d1 = 0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -347,9 +384,12 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
         const uint32_t n1 = r1 > (T)0 ? (uint32_t)r1 : 0u;
         const long long o = (long long)i * sw + j;
         if (counts) {
-          int32_t* cbase = counts + beta * counts_angle_stride;
-          cbase[(long long)p0 * sh * sw + o] = (int32_t)n0;
-          if (has1) cbase[(long long)p1 * sh * sw + o] = (int32_t)n1;
+          cbase0[(long long)t0 * sh * sw + o] = (int32_t)n0;
+          if (has1) cbase1[(long long)t1 * sh * sw + o] = (int32_t)n1;
+        }
+        if (item_counts) {
+          item_counts[(long long)p0 * sh * sw + o] = (int32_t)n0;
+          if (has1) item_counts[(long long)p1 * sh * sw + o] = (int32_t)n1;
         }
         const uint64_t wgt = splitmix64((uint64_t)o);
         d0 += (uint64_t)n0 * wgt;
@@ -360,9 +400,11 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
       d0 = wave_sum_u64(d0);
       d1 = wave_sum_u64(d1);
       if ((tid % 64) == 0 && has0) {
-        atomicAdd((unsigned long long*)&digest[beta * nq + p0], (unsigned long long)d0);
+        atomicAdd((unsigned long long*)&digest[(long long)g0 * npairs + t0],
+                  (unsigned long long)d0);
         if (has1)
-          atomicAdd((unsigned long long*)&digest[beta * nq + p1], (unsigned long long)d1);
+          atomicAdd((unsigned long long*)&digest[(long long)g1 * npairs + t1],
+                    (unsigned long long)d1);
       }
     }
   }
@@ -383,7 +425,7 @@ static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm
                      a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
                      a.sh, a.sw, a.ph, rpw, a.tw, a.logtab, a.xlogtab, a.mi,
                      a.mi_angle_stride, a.n, a.n_angle_stride, a.maxn, a.flags,
-                     a.stats);
+                     a.stats, a.gate, a.ovr, a.ovc);
   return hipGetLastError();
 }
 
@@ -395,8 +437,11 @@ static hipError_t launch_pr_bpw(const PairRowsArgs<T>& a, const PairRowsConfig& 
   return launch_pr_cfg<T, P, BPW, 1024>(a, c.nteams, c.lds, st);
 }
 
+// One (precision, FFT length) per object file: the build compiles this file
+// once per pair with CMIF_ROWS_T / CMIF_ROWS_P set, and once without them
+// for the dispatchers below, which only reference these.
 template <typename T, int P>
-static hipError_t launch_pr_p(const PairRowsArgs<T>& a, hipStream_t st) {
+hipError_t launch_pair_rows_p(const PairRowsArgs<T>& a, hipStream_t st) {
   PairRowsConfig c;
   if (!pair_rows_config(sizeof(T), P, a.QB, &c)) return hipErrorInvalidValue;
   if (c.bpw == 4) return launch_pr_bpw<T, P, 4>(a, c, st);
@@ -404,20 +449,8 @@ static hipError_t launch_pr_p(const PairRowsArgs<T>& a, hipStream_t st) {
   return launch_pr_bpw<T, P, 16>(a, c, st);
 }
 
-template <typename T>
-hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st) {
-  switch (P) {
-    case 128: return launch_pr_p<T, 128>(a, st);
-    case 256: return launch_pr_p<T, 256>(a, st);
-    case 512: return launch_pr_p<T, 512>(a, st);
-    case 1024: return launch_pr_p<T, 1024>(a, st);
-    case 2048: return launch_pr_p<T, 2048>(a, st);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename T, int P>
-static hipError_t launch_pcnt_p(const PairCountsArgs<T>& a, hipStream_t st) {
+hipError_t launch_pair_counts_p(const PairCountsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = team_for(P);
   const size_t per_team = (size_t)lds_elems(P) * sizeof(C2<T>);
   int nteams = 4;
@@ -428,22 +461,60 @@ static hipError_t launch_pcnt_p(const PairCountsArgs<T>& a, hipStream_t st) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
   if (e != hipSuccess) return e;
-  dim3 grid(a.sh, a.nb);
+  dim3 grid(a.sh, a.items ? 1 : a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
                      a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
                      a.sh, a.sw, a.ph, a.tw, a.counts, a.counts_angle_stride,
-                     a.digest);
+                     a.digest, a.items, a.n_items, a.item_counts);
   return hipGetLastError();
+}
+
+#if defined(CMIF_ROWS_T) && defined(CMIF_ROWS_P)
+
+template hipError_t launch_pair_rows_p<CMIF_ROWS_T, CMIF_ROWS_P>(
+    const PairRowsArgs<CMIF_ROWS_T>&, hipStream_t);
+template hipError_t launch_pair_counts_p<CMIF_ROWS_T, CMIF_ROWS_P>(
+    const PairCountsArgs<CMIF_ROWS_T>&, hipStream_t);
+
+#else
+
+#define CMIF_ROWS_EXTERN(T, P)                                                  \
+  extern template hipError_t launch_pair_rows_p<T, P>(const PairRowsArgs<T>&,   \
+                                                      hipStream_t);             \
+  extern template hipError_t launch_pair_counts_p<T, P>(const PairCountsArgs<T>&, \
+                                                        hipStream_t);
+CMIF_ROWS_EXTERN(float, 128)
+CMIF_ROWS_EXTERN(float, 256)
+CMIF_ROWS_EXTERN(float, 512)
+CMIF_ROWS_EXTERN(float, 1024)
+CMIF_ROWS_EXTERN(float, 2048)
+CMIF_ROWS_EXTERN(double, 128)
+CMIF_ROWS_EXTERN(double, 256)
+CMIF_ROWS_EXTERN(double, 512)
+CMIF_ROWS_EXTERN(double, 1024)
+CMIF_ROWS_EXTERN(double, 2048)
+#undef CMIF_ROWS_EXTERN
+
+template <typename T>
+hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st) {
+  switch (P) {
+    case 128: return launch_pair_rows_p<T, 128>(a, st);
+    case 256: return launch_pair_rows_p<T, 256>(a, st);
+    case 512: return launch_pair_rows_p<T, 512>(a, st);
+    case 1024: return launch_pair_rows_p<T, 1024>(a, st);
+    case 2048: return launch_pair_rows_p<T, 2048>(a, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st) {
   switch (P) {
-    case 128: return launch_pcnt_p<T, 128>(a, st);
-    case 256: return launch_pcnt_p<T, 256>(a, st);
-    case 512: return launch_pcnt_p<T, 512>(a, st);
-    case 1024: return launch_pcnt_p<T, 1024>(a, st);
-    case 2048: return launch_pcnt_p<T, 2048>(a, st);
+    case 128: return launch_pair_counts_p<T, 128>(a, st);
+    case 256: return launch_pair_counts_p<T, 256>(a, st);
+    case 512: return launch_pair_counts_p<T, 512>(a, st);
+    case 1024: return launch_pair_counts_p<T, 1024>(a, st);
+    case 2048: return launch_pair_counts_p<T, 2048>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -452,5 +523,7 @@ template hipError_t launch_pair_rows<float>(int, const PairRowsArgs<float>&, hip
 template hipError_t launch_pair_rows<double>(int, const PairRowsArgs<double>&, hipStream_t);
 template hipError_t launch_pair_counts<float>(int, const PairCountsArgs<float>&, hipStream_t);
 template hipError_t launch_pair_counts<double>(int, const PairCountsArgs<double>&, hipStream_t);
+
+#endif
 
 }  // namespace cmif

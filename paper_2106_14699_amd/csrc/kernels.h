@@ -19,6 +19,7 @@ struct FwdRowsArgs {
   C2<T>* xrow;
   long long angle_stride;
   const C2<T>* tw;  // P_w-entry table
+  const uint32_t* gate;  // nullable: angle beta runs only if gate[beta] != 0
 };
 
 template <typename T>
@@ -29,6 +30,7 @@ struct FwdColsArgs {
   C2<T>* F;
   long long f_angle_stride, f_label_stride;
   const C2<T>* tw;  // P_h-entry table
+  const uint32_t* gate;  // nullable: angle beta runs only if gate[beta] != 0
 };
 
 template <typename T>
@@ -41,6 +43,10 @@ struct PairColsArgs {
   C2<T>* Z;
   long long z_angle_stride, z_pair_stride;
   const C2<T>* tw;  // P_h-entry table
+  // item mode (nullable): one (angle, a, b) per item, Z slot = item index
+  const int4* items;
+  const uint32_t* n_items;  // device count of valid items
+  int max_items;            // grid size in item mode
 };
 
 template <typename T>
@@ -57,8 +63,14 @@ struct PairRowsArgs {
   int32_t* n;            // nullable, [nb][sh][sw]
   long long n_angle_stride;
   uint32_t* maxn;        // [nb]
-  uint32_t* flags;       // [nb][QA*QB]
+  uint32_t* flags;       // nullable, [nb][QA*QB]
   cmif_stats* stats;     // nullable
+  // FP64 re-run (all nullable): angle beta runs only if gate[beta] != 0;
+  // pair slot s = ovr[beta*QA*QB + pair] >= 0 takes its exact joint counts
+  // from ovc[s][sh][sw] instead of the rounded transform.
+  const uint32_t* gate;
+  const int32_t* ovr;
+  const int32_t* ovc;
 };
 
 template <typename T>
@@ -70,6 +82,25 @@ struct PairCountsArgs {
   int32_t* counts;       // nullable, [nb][QA*QB][sh][sw]
   long long counts_angle_stride;
   uint64_t* digest;      // nullable, [nb][QA*QB], accumulated (zero first)
+  // item mode (nullable): Z holds one pair per item slot (no angle stride);
+  // item s = (angle, a, b) writes to the (angle, a*QB+b) outputs above and,
+  // when item_counts is given, to item_counts[s][sh][sw]
+  const int4* items;
+  const uint32_t* n_items;
+  int32_t* item_counts;
+};
+
+// Compaction of the pairs that need the FP64 re-run (one workgroup).
+struct FbListArgs {
+  const uint32_t* flags;  // [nb][QA*QB]
+  int nb, QA, QB, force, capacity;
+  int4* items;            // [capacity] (angle, a, b, 0), flag order
+  uint32_t* n_items;      // min(#flagged, capacity)
+  int32_t* ovr;           // [nb][QA*QB] item slot or -1
+  uint32_t* gate;         // [nb + 1]: angle has items; [nb]: any item
+  uint32_t* maxn;         // [nb], cleared for gated angles
+  uint64_t* digest;       // nullable [nb][QA*QB], cleared for listed pairs
+  cmif_stats* stats;      // nullable
 };
 
 struct ArgmaxArgs {
@@ -143,6 +174,7 @@ hipError_t launch_check_labels(const uint8_t* lab, const uint8_t* msk,
                                long long n, int Q, cmif_stats* stats,
                                hipStream_t st);
 hipError_t launch_argmax(const ArgmaxArgs& a, hipStream_t st);
+hipError_t launch_fb_list(const FbListArgs& a, hipStream_t st);
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
 
 }  // namespace cmif
