@@ -268,6 +268,7 @@ class Plan:
         d.precision = {"fp32": CMIF_PREC_FP32_ROUNDED,
                        "fp64": CMIF_PREC_FP64}[precision]
         d.mode = {"hard": CMIF_MODE_HARD, "soft": CMIF_MODE_SOFT}[mode]
+        self.mode = mode
         d.flags = int(flags)
         d.device = self.device
         d.angle_batch = int(angle_batch)
@@ -302,23 +303,35 @@ class Plan:
         return self._ws
 
     def _inputs(self, A, MA, B, MB):
+        """HARD: A, B uint8 label images [H][W]; SOFT: float32 memberships
+        [Q][H][W].  MA, MB uint8 masks or None."""
+        import torch
         A, B = _listify(A), _listify(B)
         MA, MB = _listify(MA, len(A)), _listify(MB, len(B))
         n = len(self.sizes)
         if len(A) != n or len(B) != n:
             raise ValueError("one A and one B per image pair")
+        soft = self.mode == "soft"
         for p in range(n):
             ha, wa, hb, wb = self.sizes[p]
-            _check_tensor(A[p], (ha, wa), self.device, "A")
-            _check_tensor(B[p], (hb, wb), self.device, "B")
+            if soft:
+                _check_tensor(A[p], (self.q_a, ha, wa), self.device, "A",
+                              torch.float32)
+                _check_tensor(B[p], (self.q_b, hb, wb), self.device, "B",
+                              torch.float32)
+            else:
+                _check_tensor(A[p], (ha, wa), self.device, "A")
+                _check_tensor(B[p], (hb, wb), self.device, "B")
             if MA[p] is not None:
                 _check_tensor(MA[p], (ha, wa), self.device, "MA")
             if MB[p] is not None:
                 _check_tensor(MB[p], (hb, wb), self.device, "MB")
         keep = []
         inp = cmif_inputs()
-        for name, ts in (("labels_a", A), ("mask_a", MA), ("labels_b", B),
-                         ("mask_b", MB)):
+        names = (("memb_a", A), ("mask_a", MA), ("memb_b", B), ("mask_b", MB)) \
+            if soft else (("labels_a", A), ("mask_a", MA), ("labels_b", B),
+                          ("mask_b", MB))
+        for name, ts in names:
             ptrs = [t.data_ptr() if t is not None else 0 for t in ts]
             pa, arr = _ptr_array(ptrs)
             keep.append(arr)
@@ -413,6 +426,85 @@ class Plan:
         return res
 
 
+def _plan_backward(self, A, MA, B, MB, grad_mi, *, want_a=True, want_b=True):
+    """SOFT plans with SAVE_FOR_BACKWARD, after compute() on the same
+    inputs: dL/dA and dL/dB (float32, shapes of the memberships) for the
+    upstream dL/dMI maps grad_mi (one float64 [n_angles][S_h][S_w] tensor
+    per pair).  Returns (list or None, list or None)."""
+    torch = self._torch
+    inp, keep = self._inputs(A, MA, B, MB)
+    dev = f"cuda:{self.device}"
+    gm = _listify(grad_mi)
+    n = len(self.sizes)
+    if len(gm) != n:
+        raise ValueError("one grad_mi per image pair")
+    gm = [g.to(device=dev, dtype=torch.float64).contiguous() for g in gm]
+    for p in range(n):
+        if tuple(gm[p].shape) != (len(self.angles), *self.map_shape(p)):
+            raise ValueError("grad_mi must have shape [n_angles, S_h, S_w]")
+    ga = [torch.empty((self.q_a, s[0], s[1]), dtype=torch.float32, device=dev)
+          for s in self.sizes] if want_a else None
+    gb = [torch.empty((self.q_b, s[2], s[3]), dtype=torch.float32, device=dev)
+          for s in self.sizes] if want_b else None
+    pgm, agm = _ptr_array([t.data_ptr() for t in gm])
+    pga, aga = _ptr_array([t.data_ptr() for t in ga]) if ga else (None, None)
+    pgb, agb = _ptr_array([t.data_ptr() for t in gb]) if gb else (None, None)
+    pb, pp, sb, sp = self.workspace()
+    cmif_backward(self.handle, inp, pgm, pga, pgb, pp, self.persistent_bytes,
+                  sp, self.scratch_bytes, self._stream())
+    torch.cuda.current_stream(self.device).synchronize()
+    del keep, agm, aga, agb
+    return ga, gb
+
+
+Plan.backward = _plan_backward
+
+
+def _soft_cmif_function():
+    import torch
+
+    class SoftCMIF(torch.autograd.Function):
+        """Differentiable soft CMIF maps of one image pair: forward returns
+        the MI map [n_angles][S_h][S_w] (float64) of memberships A
+        [Q_A][H_A][W_A] and B [Q_B][H_B][W_B] (float32, on the plan's
+        device) under masks MA, MB (uint8 or None); backward runs the
+        library's adjoint.  The plan must be SOFT with SAVE_FOR_BACKWARD and
+        describe exactly one image pair."""
+
+        @staticmethod
+        def forward(ctx, A, B, plan, MA=None, MB=None):
+            A = A.detach().contiguous()
+            B = B.detach().contiguous()
+            res = plan.compute(A, MA, B, MB, mi=True, n=False)
+            ctx.plan = plan
+            ctx.save_for_backward(A, B)
+            ctx.masks = (MA, MB)
+            return res["mi"][0]
+
+        @staticmethod
+        def backward(ctx, grad_mi):
+            A, B = ctx.saved_tensors
+            MA, MB = ctx.masks
+            need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            ga, gb = ctx.plan.backward(A, MA, B, MB, grad_mi, want_a=need_a,
+                                       want_b=need_b)
+            return (ga[0] if ga else None, gb[0] if gb else None, None, None,
+                    None)
+
+    return SoftCMIF
+
+
+def soft_cmif(A, B, plan, MA=None, MB=None):
+    """MI maps of soft memberships with autograd support (see SoftCMIF)."""
+    global SoftCMIF
+    if SoftCMIF is None:
+        SoftCMIF = _soft_cmif_function()
+    return SoftCMIF.apply(A, B, plan, MA, MB)
+
+
+SoftCMIF = None
+
+
 def _listify(x, n=None):
     if isinstance(x, (list, tuple)):
         return list(x)
@@ -421,12 +513,13 @@ def _listify(x, n=None):
     return [x]
 
 
-def _check_tensor(t, shape, device, name):
+def _check_tensor(t, shape, device, name, dtype=None):
     import torch
+    dtype = torch.uint8 if dtype is None else dtype
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if t.dtype != torch.uint8 or tuple(t.shape) != tuple(shape):
-        raise ValueError(f"{name} must be uint8 of shape {shape}, got "
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be {dtype} of shape {shape}, got "
                          f"{t.dtype} {tuple(t.shape)}")
     if t.device.type != "cuda" or t.device.index != device:
         raise ValueError(f"{name} must be on cuda:{device}")

@@ -24,6 +24,8 @@ ARCH = "gfx950"
 # (precision, FFT length) so that the build runs in parallel
 SOURCES = [("api.cpp", "api", []), ("k_forward.hip", "k_forward", []),
            ("k_pair.hip", "k_pair", []), ("k_misc.hip", "k_misc", []),
+           ("k_soft.hip", "k_soft_f32", ["-DCMIF_SOFT_T=float"]),
+           ("k_soft.hip", "k_soft_f64", ["-DCMIF_SOFT_T=double"]),
            ("k_rows.hip", "k_rows", [])]
 for _t, _tn in (("float", "f32"), ("double", "f64")):
     for _p in (128, 256, 512, 1024, 2048):
@@ -55,8 +57,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
     # largest objects first
-    order = sorted(SOURCES, key=lambda e: (e[0] != "k_rows.hip" or not e[2],
-                                           -len(e[1])))
+    order = sorted(SOURCES, key=lambda e: not e[2])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, order))
     tmp = LIB + ".tmp"

@@ -51,20 +51,22 @@ struct PairPlan {
 
 struct ScratchLayout {
   size_t xa, fa, xb, fb, z, mi, n, maxn, flags, partial, running, stats;
-  // FP64 re-run (FP32 plans only)
+  // FP64 re-run (FP32 HARD plans only)
   size_t xa64, fa64, xb64, fb64, z64, cnt64, items, n_items, ovr, gate;
+  // SOFT: FP64 mask-overlap pass (one "label" per image) and the adjoint
+  size_t ov_xa, ov_fa, ov_xb, ov_fb, ov_z, zg, gh, gxa, gxb;
   size_t end;
 };
 
 enum Stage {
   ST_CHECK, ST_FWD_ROWS, ST_FWD_COLS, ST_PAIR_COLS, ST_PAIR_ROWS,
   ST_PAIR_COUNTS, ST_ARGMAX, ST_FILL, ST_TABLES, ST_FB_LIST, ST_FB_FWD,
-  ST_FB_PAIR, ST_FB_ROWS, ST_COUNT
+  ST_FB_PAIR, ST_FB_ROWS, ST_SOFT_GRAD, ST_COUNT
 };
 const char* const kStageNames[ST_COUNT] = {
     "check_labels", "fwd_rows", "fwd_cols", "pair_cols", "pair_rows",
     "pair_counts", "argmax", "fill", "tables", "fb_list", "fb_forward",
-    "fb_pairs", "fb_rows"};
+    "fb_pairs", "fb_rows", "soft_grad"};
 
 struct ProfRec {
   int stage;
@@ -99,6 +101,7 @@ struct cmif_plan_s {
   std::vector<int32_t> rc, rs;
   int batch = 1;
   int fb_cap = 0;               // FP64 re-run items per pass (FP32 plans)
+  std::vector<size_t> save_off; // SOFT + SAVE_FOR_BACKWARD: per pair
   std::vector<int> plens;       // distinct FFT lengths
   std::vector<size_t> tw_off;   // per plens entry: FP32 table, FP64 follows
   size_t logtab_off = 0;
@@ -151,6 +154,20 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
     L.n_items = take(sizeof(uint32_t));
     L.ovr = take(nb * qa * qb * sizeof(int32_t));
     L.gate = take((nb + 1) * sizeof(uint32_t));
+  }
+  if (P.d.mode == CMIF_MODE_SOFT) {
+    const size_t E64 = sizeof(double2);
+    L.ov_xa = take(half * g.ha * E64);
+    L.ov_fa = take(half * g.ph * E64);
+    L.ov_xb = take(nb * half * g.hb * E64);
+    L.ov_fb = take(nb * half * g.ph * E64);
+    L.ov_z = take(nb * half * g.sh * E64);
+    if (P.d.flags & CMIF_FLAG_SAVE_FOR_BACKWARD) {
+      L.zg = take(qa * qb * half * g.sh * E);
+      L.gh = take(qa * qb * half * g.ph * E);
+      L.gxa = take(qa * half * g.ha * E);
+      L.gxb = take(qb * half * g.hb * E);
+    }
   }
   L.end = o;
   return L;
@@ -248,22 +265,26 @@ const C2<T>* twiddles(const cmif_plan_s& P, const uint8_t* pers, int len) {
   return reinterpret_cast<const C2<T>*>(pers + off);
 }
 
-// Forward transforms of the level sets of one image for `nb` angles
-// (rotation r[b]); gate (nullable) skips angles with gate[b] == 0.
+// Forward transforms of the level sets (or soft memberships, when memb is
+// given) of one image for `nb` angles (rotation r[b]); gate (nullable) skips
+// angles with gate[b] == 0.
 template <typename T>
 cmif_status forward(cmif_plan_s& P, hipStream_t st, int stage_rows,
                      int stage_cols, const uint8_t* lab, const uint8_t* msk,
                      int H, int W, int Q, int nb, const int32_t* rc,
                      const int32_t* rs, const PairPlan& g, const uint8_t* pers,
-                     C2<T>* x, C2<T>* f, const uint32_t* gate) {
+                     C2<T>* x, C2<T>* f, const uint32_t* gate,
+                     const float* memb = nullptr, cmif_stats* stats = nullptr) {
   using CT = C2<T>;
   const int half = g.pw / 2;
   FwdRowsArgs<T> r{};
-  r.lab = lab; r.msk = msk; r.H = H; r.W = W; r.Q = Q; r.nb = nb;
+  r.lab = lab; r.msk = msk; r.memb = memb; r.stats = stats;
+  r.H = H; r.W = W; r.Q = Q; r.nb = nb;
   for (int b = 0; b < nb; ++b) { r.rot.c[b] = rc[b]; r.rot.s[b] = rs[b]; }
   r.xrow = x; r.angle_stride = (long long)Q * half * H;
   r.tw = twiddles<T>(P, pers, g.pw); r.gate = gate;
-  STAGE(stage_rows, nb * (2.0 * H * W + (double)Q * half * H * sizeof(CT)),
+  const double in_bytes = memb ? (4.0 * Q + 1.0) * H * W : 2.0 * H * W;
+  STAGE(stage_rows, nb * (in_bytes + (double)Q * half * H * sizeof(CT)),
         launch_fwd_rows<T>(g.pw, r, st));
   FwdColsArgs<T> c{};
   c.xrow = x; c.H = H; c.tiles = half / tile_width<T>(); c.Q = Q; c.nb = nb;
@@ -277,11 +298,69 @@ cmif_status forward(cmif_plan_s& P, hipStream_t st, int stage_rows,
   return CMIF_OK;
 }
 
+// Saved soft state of pair p: [n_angles][Q_A+Q_B+2][S_h][S_w] in the
+// transform precision.
+size_t save_angle_elems(const cmif_plan_s& P, const PairPlan& g) {
+  return (size_t)(P.d.q_a + P.d.q_b + 2) * g.sh * g.sw;
+}
+
+// Mask overlap N(chi) = sum_x M_A(x) M_B'(x + chi) in FP64 (one level set
+// per image): the eligibility count of SOFT plans.  Writes n and maxn.
+cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout& L,
+                         const uint8_t* ma, const uint8_t* mb, int a0, int nb,
+                         bool first, int32_t* n_ptr, uint32_t* maxn,
+                         uint32_t* flags, uint8_t* pers, uint8_t* scr,
+                         hipStream_t st) {
+  using C64 = C2<double>;
+  const int half = g.pw / 2;
+  C64* xa = reinterpret_cast<C64*>(scr + L.ov_xa);
+  C64* fa = reinterpret_cast<C64*>(scr + L.ov_fa);
+  C64* xb = reinterpret_cast<C64*>(scr + L.ov_xb);
+  C64* fb = reinterpret_cast<C64*>(scr + L.ov_fb);
+  C64* z = reinterpret_cast<C64*>(scr + L.ov_z);
+  const int32_t id_c = 65536, id_s = 0;
+  cmif_status s;
+  if (first) {
+    s = forward<double>(P, st, ST_FWD_ROWS, ST_FWD_COLS, nullptr, ma, g.ha,
+                        g.wa, 1, 1, &id_c, &id_s, g, pers, xa, fa, nullptr);
+    if (s != CMIF_OK) return s;
+  }
+  s = forward<double>(P, st, ST_FWD_ROWS, ST_FWD_COLS, nullptr, mb, g.hb, g.wb,
+                      1, nb, &P.rc[a0], &P.rs[a0], g, pers, xb, fb, nullptr);
+  if (s != CMIF_OK) return s;
+  PairColsArgs<double> pc{};
+  pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
+  pc.FB = fb; pc.fb_angle_stride = (long long)half * g.ph;
+  pc.fb_label_stride = (long long)half * g.ph;
+  pc.QA = 1; pc.QB = 1; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+  pc.tiles = half / tile_width<double>(); pc.nb = nb; pc.Z = z;
+  pc.z_angle_stride = (long long)half * g.sh;
+  pc.z_pair_stride = (long long)half * g.sh;
+  pc.tw = twiddles<double>(P, pers, g.ph);
+  STAGE(ST_PAIR_COLS, nb * (double)half * (g.ph + g.sh) * sizeof(C64),
+        launch_pair_cols<double>(g.ph, pc, st));
+  STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(maxn, 0u, nb, st));
+  STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(flags, 0u, nb, st));
+  PairRowsArgs<double> pr{};
+  pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
+  pr.QA = 1; pr.QB = 1; pr.wa = g.wa; pr.wb = g.wb;
+  pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb;
+  pr.tw = twiddles<double>(P, pers, g.pw);
+  pr.logtab = reinterpret_cast<const double*>(pers + P.logtab_off);
+  pr.xlogtab = reinterpret_cast<const double*>(pers + P.xlog_off);
+  pr.rows_per_wg = 2; pr.mi = nullptr; pr.n = n_ptr;
+  pr.n_angle_stride = (long long)g.sh * g.sw; pr.maxn = maxn; pr.flags = flags;
+  STAGE(ST_PAIR_ROWS, nb * ((double)half * g.sh * sizeof(C64) + 4.0 * g.sh * g.sw),
+        launch_pair_rows<double>(g.pw, pr, st));
+  return CMIF_OK;
+}
+
 template <typename T>
 cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
                      const uint8_t* ma, const uint8_t* lb, const uint8_t* mb,
-                     const CallOutputs& o, uint8_t* pers, uint8_t* scr,
-                     hipStream_t st) {
+                     const float* pa, const float* pb, const CallOutputs& o,
+                     uint8_t* pers, uint8_t* scr, hipStream_t st) {
+  const bool soft = P.d.mode == CMIF_MODE_SOFT;
   using CT = C2<T>;
   const PairPlan& g = P.pairs[p];
   const ScratchLayout L = layout_for(P, g);
@@ -310,7 +389,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
   cmif_best* running = reinterpret_cast<cmif_best*>(scr + L.running);
   cmif_stats* stats = o.stats;
 
-  if (stats) {
+  if (stats && !soft) {
     STAGE(ST_CHECK, 2.0 * g.ha * g.wa,
           launch_check_labels(la, ma, (long long)g.ha * g.wa, qa, stats, st));
     STAGE(ST_CHECK, 2.0 * g.hb * g.wb,
@@ -321,7 +400,8 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
   const int32_t id_c = 65536, id_s = 0;
   {
     cmif_status s = forward<T>(P, st, ST_FWD_ROWS, ST_FWD_COLS, la, ma, g.ha,
-                               g.wa, qa, 1, &id_c, &id_s, g, pers, xa, fa, nullptr);
+                               g.wa, qa, 1, &id_c, &id_s, g, pers, xa, fa,
+                               nullptr, pa, stats);
     if (s != CMIF_OK) return s;
   }
   const int nang = (int)P.angles.size();
@@ -334,7 +414,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     {
       cmif_status s = forward<T>(P, st, ST_FWD_ROWS, ST_FWD_COLS, lb, mb, g.hb,
                                  g.wb, qb, nb, &P.rc[a0], &P.rs[a0], g, pers, xb,
-                                 fb, nullptr);
+                                 fb, nullptr, pb, stats);
       if (s != CMIF_OK) return s;
     }
 
@@ -358,6 +438,26 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
 
     double* mi_ptr = o.mi ? o.mi + a0 * map_stride : mi_s;
     int32_t* n_ptr = o.n ? o.n + a0 * map_stride : n_s;
+    if (soft) {
+      SoftRowsArgs<T> sr{};
+      sr.Z = z; sr.z_angle_stride = pc.z_angle_stride; sr.z_pair_stride = pc.z_pair_stride;
+      sr.QA = qa; sr.QB = qb; sr.wa = g.wa; sr.wb = g.wb; sr.sh = g.sh; sr.sw = g.sw;
+      sr.ph = g.ph; sr.nb = nb; sr.tw = tw_w;
+      sr.mi = mi_ptr; sr.mi_angle_stride = map_stride;
+      const bool save = (P.d.flags & CMIF_FLAG_SAVE_FOR_BACKWARD) != 0;
+      const size_t sae = save_angle_elems(P, g);
+      sr.save = save ? reinterpret_cast<T*>(pers + P.save_off[p]) + a0 * sae : nullptr;
+      sr.save_angle_stride = (long long)sae;
+      STAGE(ST_PAIR_ROWS,
+            nb * ((double)qa * qb * half * g.sh * sizeof(CT) + 8.0 * g.sh * g.sw +
+                  (save ? (double)sizeof(T) * sae : 0.0)),
+            launch_soft_rows<T>(g.pw, sr, st));
+      if (o.n || want_best) {
+        cmif_status s = overlap_pass(P, g, L, ma, mb, a0, nb, a0 == 0, n_ptr,
+                                     maxn, flags, pers, scr, st);
+        if (s != CMIF_OK) return s;
+      }
+    }
     PairRowsArgs<T> pr{};
     pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
     pr.QA = qa; pr.QB = qb; pr.wa = g.wa; pr.wb = g.wb;
@@ -367,10 +467,11 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pr.n = n_ptr; pr.n_angle_stride = map_stride; pr.maxn = maxn; pr.flags = flags;
     pr.stats = stats;
     // every pair's columns read once, MI and N maps written once
-    STAGE(ST_PAIR_ROWS,
-          nb * ((double)qa * qb * half * g.sh * sizeof(CT) + 12.0 * g.sh * g.sw),
-          launch_pair_rows<T>(g.pw, pr, st));
-    if (o.counts || o.digest) {
+    if (!soft)
+      STAGE(ST_PAIR_ROWS,
+            nb * ((double)qa * qb * half * g.sh * sizeof(CT) + 12.0 * g.sh * g.sw),
+            launch_pair_rows<T>(g.pw, pr, st));
+    if (!soft && (o.counts || o.digest)) {
       PairCountsArgs<T> pk{};
       pk.Z = z; pk.z_angle_stride = pc.z_angle_stride; pk.z_pair_stride = pc.z_pair_stride;
       pk.QA = qa; pk.QB = qb; pk.wa = g.wa; pk.wb = g.wb; pk.sh = g.sh; pk.sw = g.sw;
@@ -383,7 +484,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
             launch_pair_counts<T>(g.pw, pk, st));
     }
 
-    if (!fp64 && P.fb_cap > 0) {
+    if (!soft && !fp64 && P.fb_cap > 0) {
       // FP64 re-run of the flagged pairs (everything stays on the device:
       // the list decides, the gates skip, nothing returns to the host)
       using C64 = C2<double>;
@@ -476,19 +577,7 @@ cmif_status validate_ws(const cmif_plan_s* P, void* pers, size_t pers_bytes,
   return CMIF_OK;
 }
 
-cmif_status run_hard(cmif_plan_s* P, const cmif_inputs* in,
-                     const cmif_outputs* out, cmif_best* best,
-                     cmif_best* per_angle, cmif_stats* stats, void* pers,
-                     void* scr, hipStream_t st) {
-  const int np = P->d.n_pairs;
-  if (in->labels_a == nullptr || in->labels_b == nullptr)
-    return fail(CMIF_ERR_INVALID_ARGUMENT, "labels arrays are NULL");
-  for (int p = 0; p < np; ++p)
-    if (in->labels_a[p] == nullptr || in->labels_b[p] == nullptr)
-      return fail(CMIF_ERR_INVALID_ARGUMENT, "label pointer of a pair is NULL");
-  uint8_t* pb = static_cast<uint8_t*>(pers);
-  uint8_t* sb = static_cast<uint8_t*>(scr);
-  // tables
+cmif_status init_tables(cmif_plan_s* P, uint8_t* pb, hipStream_t st) {
   cmif_plan_s& PP = *P;
   for (size_t i = 0; i < P->plens.size(); ++i) {
     const int L = P->plens[i];
@@ -501,12 +590,47 @@ cmif_status run_hard(cmif_plan_s* P, const cmif_inputs* in,
         });
     if (s != CMIF_OK) return s;
   }
+  return CMIF_OK;
+}
+
+cmif_status check_inputs(const cmif_plan_s* P, const cmif_inputs* in) {
+  const int np = P->d.n_pairs;
+  if (P->d.mode == CMIF_MODE_SOFT) {
+    if (in->memb_a == nullptr || in->memb_b == nullptr)
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "membership arrays are NULL");
+    for (int p = 0; p < np; ++p)
+      if (in->memb_a[p] == nullptr || in->memb_b[p] == nullptr)
+        return fail(CMIF_ERR_INVALID_ARGUMENT,
+                    "membership pointer of a pair is NULL");
+    return CMIF_OK;
+  }
+  if (in->labels_a == nullptr || in->labels_b == nullptr)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "labels arrays are NULL");
+  for (int p = 0; p < np; ++p)
+    if (in->labels_a[p] == nullptr || in->labels_b[p] == nullptr)
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "label pointer of a pair is NULL");
+  return CMIF_OK;
+}
+
+cmif_status run_calls(cmif_plan_s* P, const cmif_inputs* in,
+                      const cmif_outputs* out, cmif_best* best,
+                      cmif_best* per_angle, cmif_stats* stats, void* pers,
+                      void* scr, hipStream_t st) {
+  const int np = P->d.n_pairs;
+  const bool soft = P->d.mode == CMIF_MODE_SOFT;
+  cmif_status s = check_inputs(P, in);
+  if (s != CMIF_OK) return s;
+  uint8_t* pb = static_cast<uint8_t*>(pers);
+  uint8_t* sb = static_cast<uint8_t*>(scr);
+  s = init_tables(P, pb, st);
+  if (s != CMIF_OK) return s;
+  cmif_plan_s& PP = *P;
   const int nang = (int)P->angles.size();
-  if (out && out->digest) {
+  if (!soft && out && out->digest) {
     for (int p = 0; p < np; ++p)
       if (out->digest[p]) {
         const long long nw = 2LL * nang * P->d.q_a * P->d.q_b;
-        cmif_status s = launch_stage(PP, st, ST_FILL, 4.0 * nw, "fill digest", [&]() {
+        s = launch_stage(PP, st, ST_FILL, 4.0 * nw, "fill digest", [&]() {
           return launch_fill_u32(reinterpret_cast<uint32_t*>(out->digest[p]), 0u, nw, st);
         });
         if (s != CMIF_OK) return s;
@@ -517,22 +641,112 @@ cmif_status run_hard(cmif_plan_s* P, const cmif_inputs* in,
     if (out) {
       o.mi = out->mi ? out->mi[p] : nullptr;
       o.n = out->n ? out->n[p] : nullptr;
-      o.counts = out->counts ? out->counts[p] : nullptr;
-      o.digest = out->digest ? out->digest[p] : nullptr;
+      if (!soft) {
+        o.counts = out->counts ? out->counts[p] : nullptr;
+        o.digest = out->digest ? out->digest[p] : nullptr;
+      }
     }
     o.best = best ? best + p : nullptr;
     o.per_angle = per_angle ? per_angle + (size_t)p * nang : nullptr;
     o.stats = stats;
     const uint8_t* ma = in->mask_a ? in->mask_a[p] : nullptr;
     const uint8_t* mb = in->mask_b ? in->mask_b[p] : nullptr;
-    cmif_status s;
+    const uint8_t* la = soft ? nullptr : in->labels_a[p];
+    const uint8_t* lb = soft ? nullptr : in->labels_b[p];
+    const float* pa = soft ? in->memb_a[p] : nullptr;
+    const float* pbm = soft ? in->memb_b[p] : nullptr;
     if (P->d.precision == CMIF_PREC_FP64)
-      s = run_pair<double>(*P, p, in->labels_a[p], ma, in->labels_b[p], mb, o,
-                           pb, sb, st);
+      s = run_pair<double>(*P, p, la, ma, lb, mb, pa, pbm, o, pb, sb, st);
     else
-      s = run_pair<float>(*P, p, in->labels_a[p], ma, in->labels_b[p], mb, o, pb,
-                          sb, st);
+      s = run_pair<float>(*P, p, la, ma, lb, mb, pa, pbm, o, pb, sb, st);
     if (s != CMIF_OK) return s;
+  }
+  return CMIF_OK;
+}
+
+// Adjoint of the soft forward for one pair (single angle 0): the joint is
+// recomputed from the memberships, G_ab formed per displacement from the
+// saved state, transformed, summed against the other side's spectra and
+// transformed back.
+template <typename T>
+cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
+                              const uint8_t* mb, const float* pa,
+                              const float* pbm, const double* grad_mi,
+                              float* grad_a, float* grad_b, uint8_t* pers,
+                              uint8_t* scr, hipStream_t st) {
+  using CT = C2<T>;
+  const PairPlan& g = P.pairs[p];
+  const ScratchLayout L = layout_for(P, g);
+  const int qa = P.d.q_a, qb = P.d.q_b;
+  const int half = g.pw / 2;
+  const int tiles = half / tile_width<T>();
+  CT* xa = reinterpret_cast<CT*>(scr + L.xa);
+  CT* fa = reinterpret_cast<CT*>(scr + L.fa);
+  CT* xb = reinterpret_cast<CT*>(scr + L.xb);
+  CT* fb = reinterpret_cast<CT*>(scr + L.fb);
+  CT* z = reinterpret_cast<CT*>(scr + L.z);
+  CT* zg = reinterpret_cast<CT*>(scr + L.zg);
+  CT* gh = reinterpret_cast<CT*>(scr + L.gh);
+  CT* gxa = reinterpret_cast<CT*>(scr + L.gxa);
+  CT* gxb = reinterpret_cast<CT*>(scr + L.gxb);
+  const T* save = reinterpret_cast<const T*>(pers + P.save_off[p]);
+  const int32_t id_c = 65536, id_s = 0;
+  cmif_status s = forward<T>(P, st, ST_FWD_ROWS, ST_FWD_COLS, nullptr, ma, g.ha,
+                             g.wa, qa, 1, &id_c, &id_s, g, pers, xa, fa,
+                             nullptr, pa, nullptr);
+  if (s != CMIF_OK) return s;
+  s = forward<T>(P, st, ST_FWD_ROWS, ST_FWD_COLS, nullptr, mb, g.hb, g.wb, qb, 1,
+                 &P.rc[0], &P.rs[0], g, pers, xb, fb, nullptr, pbm, nullptr);
+  if (s != CMIF_OK) return s;
+  PairColsArgs<T> pc{};
+  pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
+  pc.FB = fb; pc.fb_angle_stride = (long long)qb * half * g.ph;
+  pc.fb_label_stride = (long long)half * g.ph;
+  pc.QA = qa; pc.QB = qb; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+  pc.tiles = tiles; pc.nb = 1; pc.Z = z;
+  pc.z_angle_stride = (long long)qa * qb * half * g.sh;
+  pc.z_pair_stride = (long long)half * g.sh; pc.tw = twiddles<T>(P, pers, g.ph);
+  const double zbytes = (double)qa * qb * half * g.sh * sizeof(CT);
+  STAGE(ST_PAIR_COLS,
+        (double)(qa + qb) * half * g.ph * sizeof(CT) + zbytes,
+        launch_pair_cols<T>(g.ph, pc, st));
+  SoftGradRowsArgs<T> gr{};
+  gr.Z = z; gr.z_pair_stride = pc.z_pair_stride; gr.QA = qa; gr.QB = qb;
+  gr.wa = g.wa; gr.wb = g.wb; gr.sh = g.sh; gr.sw = g.sw; gr.ph = g.ph;
+  gr.tw = twiddles<T>(P, pers, g.pw); gr.grad_mi = grad_mi; gr.save = save;
+  gr.ZG = zg;
+  STAGE(ST_SOFT_GRAD,
+        2.0 * zbytes + (8.0 + (double)sizeof(T) * (qa + qb + 2)) * g.sh * g.sw,
+        launch_soft_grad_rows<T>(g.pw, gr, st));
+  FwdColsArgs<T> gc{};
+  gc.xrow = zg; gc.H = g.sh; gc.tiles = tiles; gc.Q = qa * qb; gc.nb = 1;
+  gc.x_angle_stride = 0; gc.x_label_stride = (long long)half * g.sh;
+  gc.F = gh; gc.f_angle_stride = 0; gc.f_label_stride = (long long)half * g.ph;
+  gc.tw = twiddles<T>(P, pers, g.ph); gc.circ_ha = g.ha; gc.circ_hb = g.hb;
+  STAGE(ST_SOFT_GRAD, zbytes + (double)qa * qb * half * g.ph * sizeof(CT),
+        launch_fwd_cols<T>(g.ph, gc, st));
+  for (int side = 0; side < 2; ++side) {
+    float* grad = side == 0 ? grad_a : grad_b;
+    if (grad == nullptr) continue;
+    const int q = side == 0 ? qa : qb;
+    const int H = side == 0 ? g.ha : g.hb, W = side == 0 ? g.wa : g.wb;
+    CT* gx = side == 0 ? gxa : gxb;
+    SoftGradColsArgs<T> sc{};
+    sc.GH = gh; sc.FO = side == 0 ? fb : fa;
+    sc.f_label_stride = (long long)half * g.ph; sc.QA = qa; sc.QB = qb;
+    sc.H = H; sc.tiles = tiles; sc.side = side; sc.GX = gx;
+    sc.gx_label_stride = (long long)half * H; sc.tw = twiddles<T>(P, pers, g.ph);
+    STAGE(ST_SOFT_GRAD,
+          ((double)qa * qb + (side == 0 ? qb : qa)) * half * g.ph * sizeof(CT) +
+              (double)q * half * H * sizeof(CT),
+          launch_soft_grad_cols<T>(g.ph, sc, st));
+    SoftGradOutArgs<T> so{};
+    so.GX = gx; so.gx_label_stride = (long long)half * H; so.Q = q; so.H = H;
+    so.W = W; so.ph = g.ph; so.msk = side == 0 ? ma : mb;
+    so.tw = twiddles<T>(P, pers, g.pw); so.grad = grad;
+    STAGE(ST_SOFT_GRAD,
+          (double)q * half * H * sizeof(CT) + (4.0 * q + 1.0) * H * W,
+          launch_soft_grad_out<T>(g.pw, so, st));
   }
   return CMIF_OK;
 }
@@ -624,8 +838,13 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
     return fail(CMIF_ERR_INVALID_ARGUMENT, "angle_batch must be >= 0");
   if (d->fallback_capacity < 0 || d->fallback_capacity > 4096)
     return fail(CMIF_ERR_INVALID_ARGUMENT, "fallback_capacity must be in [0, 4096]");
-  if (d->mode == CMIF_MODE_SOFT)
-    return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
+  if (d->mode == CMIF_MODE_SOFT && (d->flags & CMIF_FLAG_SAVE_FOR_BACKWARD)) {
+    const bool identity = d->n_angles == 1 &&
+                          (d->angles_rad == nullptr || d->angles_rad[0] == 0.0);
+    if (!identity)
+      return fail(CMIF_ERR_UNSUPPORTED,
+                  "SAVE_FOR_BACKWARD supports the single angle 0 only");
+  }
 
   cmif_plan_s* P = new (std::nothrow) cmif_plan_s();
   if (!P) return fail(CMIF_ERR_HOST_MEMORY, "plan allocation failed");
@@ -649,8 +868,13 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
       return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 2048");
     }
     PairRowsConfig rc;
+    SoftRowsConfig sc;
     const size_t er = d->precision == CMIF_PREC_FP64 ? sizeof(double) : sizeof(float);
-    if (!pair_rows_config(er, g.pw, d->q_b, &rc)) {
+    const bool fits = d->mode == CMIF_MODE_SOFT
+                          ? soft_rows_config(er, g.pw, d->q_b, &sc) &&
+                                pair_rows_config(sizeof(double), g.pw, 1, &rc)
+                          : pair_rows_config(er, g.pw, d->q_b, &rc);
+    if (!fits) {
       delete P;
       return fail(CMIF_ERR_UNSUPPORTED,
                   "q_b too large for the row kernel at this FFT length");
@@ -684,7 +908,7 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   batch = std::min(batch, kMaxBatch);
   batch = std::min(batch, d->n_angles);
   P->batch = std::max(batch, 1);
-  if (d->precision == CMIF_PREC_FP32_ROUNDED) {
+  if (d->precision == CMIF_PREC_FP32_ROUNDED && d->mode == CMIF_MODE_HARD) {
     const int per_pass = P->batch * d->q_a * d->q_b;
     const int cap = d->fallback_capacity > 0 ? d->fallback_capacity : 64;
     P->fb_cap = std::min(cap, per_pass);
@@ -699,6 +923,13 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   o += up256(512 * sizeof(double));
   P->xlog_off = o;
   o += up256(kXlogN * sizeof(double));
+  if (d->mode == CMIF_MODE_SOFT && (d->flags & CMIF_FLAG_SAVE_FOR_BACKWARD)) {
+    for (const auto& g : P->pairs) {
+      P->save_off.push_back(o);
+      const size_t er = d->precision == CMIF_PREC_FP64 ? sizeof(double) : sizeof(float);
+      o += up256(save_angle_elems(*P, g) * P->angles.size() * er);
+    }
+  }
   P->persistent_bytes = o;
   size_t smax = 0;
   for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);
@@ -728,13 +959,13 @@ cmif_status cmif_compute(cmif_plan_t plan, const cmif_inputs* in,
   cmif_status s = validate_ws(plan, persistent, persistent_bytes, scratch,
                               scratch_bytes);
   if (s != CMIF_OK) return s;
-  if (plan->d.mode != CMIF_MODE_HARD)
-    return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
+  s = check_inputs(plan, in);
+  if (s != CMIF_OK) return s;
   s = check_device(plan);
   if (s != CMIF_OK) return s;
   DeviceGuard dg(plan->d.device);
   if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
-  return run_hard(plan, in, out, out ? out->best : nullptr,
+  return run_calls(plan, in, out, out ? out->best : nullptr,
                   out ? out->per_angle : nullptr, out ? out->stats : nullptr,
                   persistent, scratch, static_cast<hipStream_t>(stream));
 }
@@ -750,13 +981,13 @@ cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
   cmif_status s = validate_ws(plan, persistent, persistent_bytes, scratch,
                               scratch_bytes);
   if (s != CMIF_OK) return s;
-  if (plan->d.mode != CMIF_MODE_HARD)
-    return fail(CMIF_ERR_WRONG_MODE, "cmif_align needs a HARD plan");
+  s = check_inputs(plan, in);
+  if (s != CMIF_OK) return s;
   s = check_device(plan);
   if (s != CMIF_OK) return s;
   DeviceGuard dg(plan->d.device);
   if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
-  return run_hard(plan, in, nullptr, best, per_angle, stats, persistent,
+  return run_calls(plan, in, nullptr, best, per_angle, stats, persistent,
                   scratch, static_cast<hipStream_t>(stream));
 }
 
@@ -766,14 +997,44 @@ cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
                           size_t persistent_bytes, void* scratch,
                           size_t scratch_bytes, void* stream) {
   g_err.clear();
-  (void)in; (void)grad_mi; (void)grad_a; (void)grad_b; (void)persistent;
-  (void)persistent_bytes; (void)scratch; (void)scratch_bytes; (void)stream;
   if (!plan) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan");
   if (plan->d.mode != CMIF_MODE_SOFT ||
       !(plan->d.flags & CMIF_FLAG_SAVE_FOR_BACKWARD))
     return fail(CMIF_ERR_WRONG_MODE,
                 "cmif_backward needs a SOFT plan with SAVE_FOR_BACKWARD");
-  return fail(CMIF_ERR_UNSUPPORTED, "SOFT mode is not available yet");
+  if (!in || !grad_mi) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL inputs or grad_mi");
+  cmif_status s = validate_ws(plan, persistent, persistent_bytes, scratch,
+                              scratch_bytes);
+  if (s != CMIF_OK) return s;
+  s = check_inputs(plan, in);
+  if (s != CMIF_OK) return s;
+  for (int p = 0; p < plan->d.n_pairs; ++p)
+    if (grad_mi[p] == nullptr)
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "grad_mi pointer of a pair is NULL");
+  s = check_device(plan);
+  if (s != CMIF_OK) return s;
+  DeviceGuard dg(plan->d.device);
+  if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint8_t* pb = static_cast<uint8_t*>(persistent);
+  uint8_t* sb = static_cast<uint8_t*>(scratch);
+  s = init_tables(plan, pb, st);
+  if (s != CMIF_OK) return s;
+  for (int p = 0; p < plan->d.n_pairs; ++p) {
+    const uint8_t* ma = in->mask_a ? in->mask_a[p] : nullptr;
+    const uint8_t* mb = in->mask_b ? in->mask_b[p] : nullptr;
+    float* ga = grad_a ? grad_a[p] : nullptr;
+    float* gb = grad_b ? grad_b[p] : nullptr;
+    if (!ga && !gb) continue;
+    if (plan->d.precision == CMIF_PREC_FP64)
+      s = run_backward_pair<double>(*plan, p, ma, mb, in->memb_a[p], in->memb_b[p],
+                                    grad_mi[p], ga, gb, pb, sb, st);
+    else
+      s = run_backward_pair<float>(*plan, p, ma, mb, in->memb_a[p], in->memb_b[p],
+                                   grad_mi[p], ga, gb, pb, sb, st);
+    if (s != CMIF_OK) return s;
+  }
+  return CMIF_OK;
 }
 
 }  // extern "C"

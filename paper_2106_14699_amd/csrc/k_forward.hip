@@ -3,7 +3,8 @@
 //
 // k_fwd_rows: one workgroup per image row (and angle).  Each lane resamples
 //   its pixels of the row by the fixed-point nearest-neighbour rotation
-//   (Sec. 3.6), then every team transforms two level sets at once: the
+//   (Sec. 3.6), then every team transforms two level sets (or, for soft
+//   memberships, two membership channels times the mask) at once: the
 //   complex input L_a + i L_{a+1} (zero-padded to P_w) goes through one
 //   forward FFT and the two real spectra are separated with the Hermitian
 //   mirror X(P - k).  Output: X[label][tile][y][TW], k_x in [0, P_w/2) with
@@ -11,7 +12,9 @@
 // k_fwd_cols: one workgroup per (tile of TW columns, label, angle); the tile
 //   (H rows x 64 B) is read coalesced into LDS, each team transforms one
 //   column along y (zero-padded to P_h) and writes it contiguously as
-//   F[label][c][k_y].
+//   F[label][c][k_y].  In circular mode the H rows are displacement-map rows
+//   and go to their circular positions (the soft adjoint transforms its
+//   per-displacement weights this way).
 #include "fft_core.h"
 #include "internal.h"
 #include "kernels.h"
@@ -26,9 +29,10 @@ __device__ __forceinline__ int floordiv_pos_pow2(long long a, int shift) {
 template <typename T, int P, int TEAM>
 __global__ void __launch_bounds__(4 * TEAM)
 k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
-           int H, int W, int Q, RotArgs rot, C2<T>* __restrict__ xrow,
-           long long angle_stride, const C2<T>* __restrict__ tw,
-           const uint32_t* __restrict__ gate) {
+           const float* __restrict__ memb, int H, int W, int Q, RotArgs rot,
+           C2<T>* __restrict__ xrow, long long angle_stride,
+           const C2<T>* __restrict__ tw, const uint32_t* __restrict__ gate,
+           cmif_stats* __restrict__ stats) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int R = P / TEAM;
@@ -45,11 +49,14 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
   fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
   const long long c = rot.c[beta], s = rot.s[beta];
   const long long one = 65536;
+  // per pixel of the row: source index in the unrotated image inside the
+  // mask, or -1; hard labels resolve it to the label (255 = no level set)
+  int srci[R];
   uint8_t lv[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int x = lane + TEAM * q;
-    uint8_t l = 255;
+    int si = -1;
     if (x < W) {
       const long long X = 2LL * x - (W - 1);
       const long long Y = 2LL * y - (H - 1);
@@ -59,11 +66,15 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
       const int ys = floordiv_pos_pow2(ys2 + (long long)(H - 1) * one + one, 17);
       if (xs >= 0 && xs < W && ys >= 0 && ys < H) {
         const int src = ys * W + xs;
-        if (msk == nullptr || msk[src]) {
-          const uint8_t v = lab[src];
-          if (v < Q) l = v;
-        }
+        if (msk == nullptr || msk[src]) si = src;
       }
+    }
+    srci[q] = si;
+    uint8_t l = 255;
+    if (memb == nullptr && si >= 0) {
+      // no label image: every in-mask pixel is label 0 (mask overlap counts)
+      const uint8_t v = lab ? lab[si] : (uint8_t)0;
+      if (v < Q) l = v;
     }
     lv[q] = l;
   }
@@ -71,15 +82,32 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
   const int npacks = (Q + 1) / 2;
   const int iters = (npacks + nteams - 1) / nteams;
   const long long plane = (long long)(P / 2) * H;  // elements per label
+  const long long hw = (long long)H * W;
   C2<T>* out = xrow + beta * angle_stride;
+  uint32_t bad = 0u;
   for (int it = 0; it < iters; ++it) {
     const int pk = team + it * nteams;
     const bool active = pk < npacks;
     const int a0 = 2 * pk, a1 = 2 * pk + 1;
     C2<T> v[R];
+    if (memb == nullptr) {
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      v[q] = mk<T>(lv[q] == a0 ? (T)1 : (T)0, lv[q] == a1 ? (T)1 : (T)0);
+      for (int q = 0; q < R; ++q)
+        v[q] = mk<T>(lv[q] == a0 ? (T)1 : (T)0, lv[q] == a1 ? (T)1 : (T)0);
+    } else {
+      // soft memberships in place of the indicators (non-finite -> 0)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        float m0 = 0.0f, m1 = 0.0f;
+        if (active && srci[q] >= 0) {
+          m0 = memb[(long long)a0 * hw + srci[q]];
+          if (a1 < Q) m1 = memb[(long long)a1 * hw + srci[q]];
+          if (!isfinite(m0)) { m0 = 0.0f; ++bad; }
+          if (!isfinite(m1)) { m1 = 0.0f; ++bad; }
+        }
+        v[q] = mk<T>((T)m0, (T)m1);
+      }
+    }
     team_fft<T, P, TEAM, -1>(v, lds, ftw, lane);
 #pragma unroll
     for (int q = 0; q < R; ++q) lds[lpad(lane + TEAM * q)] = v[q];
@@ -110,6 +138,11 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
       }
     }
   }
+  if (memb != nullptr && stats != nullptr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((threadIdx.x % 64) == 0 && bad) atomicAdd(&stats->nonfinite_inputs, bad);
+  }
 }
 
 template <typename T, int P, int TEAM>
@@ -117,7 +150,8 @@ __global__ void __launch_bounds__(tile_width<T>() * TEAM)
 k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
            long long x_label_stride, C2<T>* __restrict__ F,
            long long f_angle_stride, long long f_label_stride,
-           const C2<T>* __restrict__ tw, const uint32_t* __restrict__ gate) {
+           const C2<T>* __restrict__ tw, const uint32_t* __restrict__ gate,
+           int circ_ha, int circ_hb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int R = P / TEAM;
@@ -145,7 +179,10 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int y = lane + TEAM * q;
-    v[q] = y < H ? smem[y * TW + (team ^ stage_swz<TW>(y))] : mk<T>((T)0, (T)0);
+    // source row of position y: the row itself, or (circular mode) the map
+    // row whose displacement is y mod P_h
+    const int sr = circ_ha > 0 ? circ_to_map(y, P, circ_ha, circ_hb) : (y < H ? y : -1);
+    v[q] = sr >= 0 ? smem[sr * TW + (team ^ stage_swz<TW>(sr))] : mk<T>((T)0, (T)0);
   }
   __syncthreads();
   team_fft<T, P, TEAM, -1>(v, smem + team * lds_elems(P), ftw, lane);
@@ -175,8 +212,9 @@ static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
                                      (int)shm);
   if (e != hipSuccess) return e;
   dim3 grid(a.H, a.nb);
-  hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.lab, a.msk, a.H,
-                     a.W, a.Q, a.rot, a.xrow, a.angle_stride, a.tw, a.gate);
+  hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.lab, a.msk,
+                     a.memb, a.H, a.W, a.Q, a.rot, a.xrow, a.angle_stride, a.tw,
+                     a.gate, a.stats);
   return hipGetLastError();
 }
 
@@ -205,7 +243,7 @@ static hipError_t launch_cols_p(const FwdColsArgs<T>& a, hipStream_t st) {
   dim3 grid(a.tiles, a.Q, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.xrow, a.H,
                      a.x_angle_stride, a.x_label_stride, a.F, a.f_angle_stride,
-                     a.f_label_stride, a.tw, a.gate);
+                     a.f_label_stride, a.tw, a.gate, a.circ_ha, a.circ_hb);
   return hipGetLastError();
 }
 

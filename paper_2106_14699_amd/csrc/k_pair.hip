@@ -11,16 +11,9 @@
 #include "fft_core.h"
 #include "internal.h"
 #include "kernels.h"
+#include "rows_common.h"
 
 namespace cmif {
-
-// Separate the packed column 0: W = G0 + i G1 with G0, G1 Hermitian in k.
-template <typename T>
-__device__ __forceinline__ void unpack0(C2<T> w, C2<T> wm, C2<T>& g0, C2<T>& g1) {
-  // g0 = (w + conj(wm)) / 2,  g1 = (w - conj(wm)) / (2i)
-  g0 = mk<T>((w.x + wm.x) * (T)0.5, (w.y - wm.y) * (T)0.5);
-  g1 = mk<T>((w.y + wm.y) * (T)0.5, (wm.x - w.x) * (T)0.5);
-}
 
 // LDS of the column kernel: the teams' exchange buffers (re-used as the
 // staging tile) and, when it fits, the twiddle table (otherwise every lane

@@ -23,77 +23,9 @@
 #include "fft_core.h"
 #include "internal.h"
 #include "kernels.h"
+#include "rows_common.h"
 
 namespace cmif {
-
-template <typename T>
-__device__ __forceinline__ T round_half_even(T v);
-template <>
-__device__ __forceinline__ float round_half_even<float>(float v) { return rintf(v); }
-template <>
-__device__ __forceinline__ double round_half_even<double>(double v) { return rint(v); }
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Raw loads of row i of pairs p0 (and p1 when has1): element k of the half
-// spectrum that lane position k = lane + TEAM*q needs (its mirror P - k in
-// the upper half; slot 0 for k = 0 and k = P/2).
-template <typename T, int P, int TEAM>
-__device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
-                                         const C2<T>* __restrict__ z1,
-                                         bool has1, int tile_stride, int lane,
-                                         C2<T> (&u0)[P / TEAM],
-                                         C2<T> (&u1)[P / TEAM]) {
-  constexpr int R = P / TEAM;
-  constexpr int TW = tile_width<T>();
-  constexpr int HALF = P / 2;
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int k = lane + TEAM * q;
-    const int kk = k > HALF ? P - k : k;
-    const int e = kk == HALF ? 0 : kk;
-    const int off = (e / TW) * tile_stride + (e % TW);
-    u0[q] = z0[off];
-    u1[q] = has1 ? z1[off] : mk<T>((T)0, (T)0);
-  }
-}
-
-// Packed complex sequence W(k) = Z_p0(k) + i Z_p1(k) from the raw loads
-// (Hermitian extension of both half spectra).
-template <typename T, int P, int TEAM>
-__device__ __forceinline__ void build_pack(const C2<T> (&u0)[P / TEAM],
-                                           const C2<T> (&u1)[P / TEAM], int lane,
-                                           C2<T> (&w)[P / TEAM]) {
-  constexpr int R = P / TEAM;
-  constexpr int HALF = P / 2;
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int k = lane + TEAM * q;
-    const int kk = k > HALF ? P - k : k;
-    if (kk == 0)
-      w[q] = mk<T>(u0[q].x, u1[q].x);
-    else if (kk == HALF)
-      w[q] = mk<T>(u0[q].y, u1[q].y);
-    else if (k < HALF)
-      w[q] = mk<T>(u0[q].x - u1[q].y, u0[q].y + u1[q].x);  // u0 + i u1
-    else
-      w[q] = mk<T>(u0[q].x + u1[q].y, u1[q].x - u0[q].y);  // conj(u0) + i conj(u1)
-  }
-}
-
-template <typename T, int P, int TEAM>
-__device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
-                                          const C2<T>* __restrict__ z1,
-                                          bool has1, int tile_stride, int lane,
-                                          C2<T> (&w)[P / TEAM]) {
-  C2<T> u0[P / TEAM], u1[P / TEAM];
-  load_raw<T, P, TEAM>(z0, z1, has1, tile_stride, lane, u0, u1);
-  build_pack<T, P, TEAM>(u0, u1, lane, w);
-}
 
 template <typename T, int P, int TEAM, int BPW, int NTMAX>
 __global__ void __launch_bounds__(NTMAX)

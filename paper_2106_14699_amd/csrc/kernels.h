@@ -12,8 +12,10 @@ namespace cmif {
 
 template <typename T>
 struct FwdRowsArgs {
-  const uint8_t* lab;
+  const uint8_t* lab;  // nullable: every in-mask pixel has label 0
   const uint8_t* msk;  // nullable
+  const float* memb;   // nullable: soft memberships [Q][H][W] replace lab
+  cmif_stats* stats;   // nullable (soft: non-finite memberships)
   int H, W, Q, nb;
   RotArgs rot;
   C2<T>* xrow;
@@ -31,6 +33,9 @@ struct FwdColsArgs {
   long long f_angle_stride, f_label_stride;
   const C2<T>* tw;  // P_h-entry table
   const uint32_t* gate;  // nullable: angle beta runs only if gate[beta] != 0
+  // circular mode (circ_ha > 0): the H = S_h input rows are map rows of an
+  // (h_a, h_b) displacement map, placed at their circular positions
+  int circ_ha, circ_hb;
 };
 
 template <typename T>
@@ -88,6 +93,52 @@ struct PairCountsArgs {
   const int4* items;
   const uint32_t* n_items;
   int32_t* item_counts;
+};
+
+// Soft row pass (real joints, no rounding).
+template <typename T>
+struct SoftRowsArgs {
+  const C2<T>* Z;
+  long long z_angle_stride, z_pair_stride;
+  int QA, QB, wa, wb, sh, sw, ph, nb;
+  const C2<T>* tw;       // P_w-entry table
+  double* mi;            // nullable, [nb][sh][sw]
+  long long mi_angle_stride;
+  T* save;               // nullable, [nb][QA+QB+2][sh][sw] adjoint state
+  long long save_angle_stride;
+};
+
+// Soft adjoint passes (one angle).
+template <typename T>
+struct SoftGradRowsArgs {
+  const C2<T>* Z;        // pair columns of the forward pass
+  long long z_pair_stride;
+  int QA, QB, wa, wb, sh, sw, ph;
+  const C2<T>* tw;       // P_w-entry table
+  const double* grad_mi; // [sh][sw] dL/dMI
+  const T* save;         // [QA+QB+2][sh][sw]
+  C2<T>* ZG;             // out: half spectra of G, layout of Z
+};
+
+template <typename T>
+struct SoftGradColsArgs {
+  const C2<T>* GH;       // [QA*QB][P_w/2][P_h] 2D spectra of G
+  const C2<T>* FO;       // other side's spectra [Q][P_w/2][P_h]
+  long long f_label_stride;
+  int QA, QB, H, tiles, side;  // side 0: gradient of A, 1: of B
+  C2<T>* GX;             // out: [Q_side][tile][H][TW] row spectra
+  long long gx_label_stride;
+  const C2<T>* tw;       // P_h-entry table
+};
+
+template <typename T>
+struct SoftGradOutArgs {
+  const C2<T>* GX;
+  long long gx_label_stride;
+  int Q, H, W, ph;
+  const uint8_t* msk;    // nullable
+  const C2<T>* tw;       // P_w-entry table
+  float* grad;           // out: [Q][H][W]
 };
 
 // Compaction of the pairs that need the FP64 re-run (one workgroup).
@@ -156,6 +207,30 @@ inline bool pair_rows_config(size_t elem_real, int P, int QB, PairRowsConfig* c)
   return false;
 }
 
+// Block shape of the soft row kernel (bpw 4 or 8, double accumulators).
+struct SoftRowsConfig {
+  int bpw, nteams, ntmax;
+  size_t lds;
+};
+
+inline bool soft_rows_config(size_t elem_real, int P, int QB, SoftRowsConfig* c) {
+  const int team = team_for(P);
+  for (int bpw : {4, 8}) {
+    const int nteams = (QB + bpw - 1) / bpw;
+    const int nt = nteams * team;
+    if (nt > 1024) continue;
+    const size_t lds = (size_t)nteams * lds_elems(P) * 2 * elem_real +
+                       2 * (size_t)P * sizeof(double);
+    if (lds > 160 * 1024) continue;
+    c->bpw = bpw;
+    c->nteams = nteams;
+    c->ntmax = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
+    c->lds = lds;
+    return true;
+  }
+  return false;
+}
+
 template <typename T>
 hipError_t launch_fwd_rows(int P, const FwdRowsArgs<T>& a, hipStream_t st);
 template <typename T>
@@ -166,6 +241,15 @@ template <typename T>
 hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st);
+
+template <typename T>
+hipError_t launch_soft_rows(int P, const SoftRowsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_soft_grad_rows(int P, const SoftGradRowsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_soft_grad_cols(int P, const SoftGradColsArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_soft_grad_out(int P, const SoftGradOutArgs<T>& a, hipStream_t st);
 
 hipError_t launch_init_tables(void* tw32, void* tw64, int P, double* logtab,
                               double* xlogtab, hipStream_t st);

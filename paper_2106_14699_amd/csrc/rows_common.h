@@ -1,0 +1,88 @@
+// Device helpers shared by the pair and row passes: separation of the
+// packed column 0, loads of two stored half-spectrum rows and their
+// Hermitian extension into one packed complex sequence.
+#pragma once
+
+#include "fft_core.h"
+#include "internal.h"
+
+namespace cmif {
+
+// Separate the packed column 0: W = G0 + i G1 with G0, G1 Hermitian in k.
+template <typename T>
+__device__ __forceinline__ void unpack0(C2<T> w, C2<T> wm, C2<T>& g0, C2<T>& g1) {
+  // g0 = (w + conj(wm)) / 2,  g1 = (w - conj(wm)) / (2i)
+  g0 = mk<T>((w.x + wm.x) * (T)0.5, (w.y - wm.y) * (T)0.5);
+  g1 = mk<T>((w.y + wm.y) * (T)0.5, (wm.x - w.x) * (T)0.5);
+}
+
+template <typename T>
+__device__ __forceinline__ T round_half_even(T v);
+template <>
+__device__ __forceinline__ float round_half_even<float>(float v) { return rintf(v); }
+template <>
+__device__ __forceinline__ double round_half_even<double>(double v) { return rint(v); }
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Raw loads of row i of pairs p0 (and p1 when has1): element k of the half
+// spectrum that lane position k = lane + TEAM*q needs (its mirror P - k in
+// the upper half; slot 0 for k = 0 and k = P/2).
+template <typename T, int P, int TEAM>
+__device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
+                                         const C2<T>* __restrict__ z1,
+                                         bool has1, int tile_stride, int lane,
+                                         C2<T> (&u0)[P / TEAM],
+                                         C2<T> (&u1)[P / TEAM]) {
+  constexpr int R = P / TEAM;
+  constexpr int TW = tile_width<T>();
+  constexpr int HALF = P / 2;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+    const int kk = k > HALF ? P - k : k;
+    const int e = kk == HALF ? 0 : kk;
+    const int off = (e / TW) * tile_stride + (e % TW);
+    u0[q] = z0[off];
+    u1[q] = has1 ? z1[off] : mk<T>((T)0, (T)0);
+  }
+}
+
+// Packed complex sequence W(k) = Z_p0(k) + i Z_p1(k) from the raw loads
+// (Hermitian extension of both half spectra).
+template <typename T, int P, int TEAM>
+__device__ __forceinline__ void build_pack(const C2<T> (&u0)[P / TEAM],
+                                           const C2<T> (&u1)[P / TEAM], int lane,
+                                           C2<T> (&w)[P / TEAM]) {
+  constexpr int R = P / TEAM;
+  constexpr int HALF = P / 2;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+    const int kk = k > HALF ? P - k : k;
+    if (kk == 0)
+      w[q] = mk<T>(u0[q].x, u1[q].x);
+    else if (kk == HALF)
+      w[q] = mk<T>(u0[q].y, u1[q].y);
+    else if (k < HALF)
+      w[q] = mk<T>(u0[q].x - u1[q].y, u0[q].y + u1[q].x);  // u0 + i u1
+    else
+      w[q] = mk<T>(u0[q].x + u1[q].y, u1[q].x - u0[q].y);  // conj(u0) + i conj(u1)
+  }
+}
+
+template <typename T, int P, int TEAM>
+__device__ __forceinline__ void load_pack(const C2<T>* __restrict__ z0,
+                                          const C2<T>* __restrict__ z1,
+                                          bool has1, int tile_stride, int lane,
+                                          C2<T> (&w)[P / TEAM]) {
+  C2<T> u0[P / TEAM], u1[P / TEAM];
+  load_raw<T, P, TEAM>(z0, z1, has1, tile_stride, lane, u0, u1);
+  build_pack<T, P, TEAM>(u0, u1, lane, w);
+}
+
+}  // namespace cmif

@@ -221,10 +221,21 @@ def random_case(seed: int, ha: int, wa: int, hb: int, wb: int, qa: int,
 
 
 def random_soft_case(seed: int, ha: int, wa: int, hb: int, wb: int, q: int,
-                     temp: float = 0.5, smooth: float = 1.5):
+                     temp: float = 0.5, smooth: float = 1.5,
+                     qb: int | None = None,
+                     mask_density: float | None = None):
+    """Soft memberships: softmax over channels (temperature temp) of blurred
+    N(0,1) logits, q channels for A and qb (default q) for B; masks all ones
+    or i.i.d. Bernoulli(mask_density)."""
     rng = np.random.default_rng(seed)
+    qb = q if qb is None else qb
     za = np.stack([field(rng, smooth, (ha, wa)) for _ in range(q)])
-    zb = np.stack([field(rng, smooth, (hb, wb)) for _ in range(q)])
+    zb = np.stack([field(rng, smooth, (hb, wb)) for _ in range(qb)])
+    if mask_density is None:
+        ma = np.ones((ha, wa), np.uint8)
+        mb = np.ones((hb, wb), np.uint8)
+    else:
+        ma = (rng.random((ha, wa)) < mask_density).astype(np.uint8)
+        mb = (rng.random((hb, wb)) < mask_density).astype(np.uint8)
     return dict(PA=softmax0(za, temp).astype(np.float32),
-                PB=softmax0(zb, temp).astype(np.float32),
-                MA=np.ones((ha, wa), np.uint8), MB=np.ones((hb, wb), np.uint8))
+                PB=softmax0(zb, temp).astype(np.float32), MA=ma, MB=mb)

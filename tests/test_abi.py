@@ -107,7 +107,8 @@ def plan_status(cm, d):
     ("q_a", 0, 1), ("q_a", 65, 1), ("q_b", 0, 1), ("gamma", -0.1, 1),
     ("gamma", 1.5, 1), ("gamma", float("nan"), 1), ("precision", 7, 1),
     ("mode", 3, 1), ("flags", 1 << 20, 1), ("n_pairs", 0, 1),
-    ("n_angles", 0, 1), ("angle_batch", -1, 1),
+    ("n_angles", 0, 1), ("angle_batch", -1, 1), ("fallback_capacity", -1, 1),
+    ("fallback_capacity", 4097, 1),
 ])
 def test_plan_rejects_bad_fields(cm, field, value, expect):
     d = make_desc(cm)
@@ -186,6 +187,52 @@ def test_calls_validate_before_device_work(cm):
     finally:
         cm.cmif_plan_free(h)
     cm.cmif_plan_free(0)  # NULL is ignored
+
+
+def test_soft_plans(cm):
+    save = cm.CMIF_FLAG_SAVE_FOR_BACKWARD
+    d = make_desc(cm, sizes=((40, 36, 33, 45),), qa=3, qb=4)
+    d.mode = cm.CMIF_MODE_SOFT
+    assert plan_status(cm, d) == 0
+    # the adjoint takes the single angle 0 only
+    d = make_desc(cm, angles=(0.0, 0.5))
+    d.mode, d.flags = cm.CMIF_MODE_SOFT, save
+    assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
+    d = make_desc(cm, angles=(0.25,))
+    d.mode, d.flags = cm.CMIF_MODE_SOFT, save
+    assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
+    # saved state lives in the persistent workspace:
+    # (q_a + q_b + 2) float planes of the 72 x 80 map
+    sizes = ((40, 36, 33, 45),)
+    d0 = make_desc(cm, sizes=sizes, qa=3, qb=4)
+    d0.mode = cm.CMIF_MODE_SOFT
+    d1 = make_desc(cm, sizes=sizes, qa=3, qb=4)
+    d1.mode, d1.flags = cm.CMIF_MODE_SOFT, save
+    h0, h1 = cm.cmif_plan(d0), cm.cmif_plan(d1)
+    try:
+        p0, s0 = cm.cmif_workspace_size(h0)
+        p1, s1 = cm.cmif_workspace_size(h1)
+        assert p1 - p0 >= (3 + 4 + 2) * 72 * 80 * 4
+        lib = cm._lib
+        inp = cm.cmif_inputs()
+        # backward needs SAVE_FOR_BACKWARD; then NULL memberships are caught
+        assert lib.cmif_backward(ctypes.c_void_p(h0), ctypes.byref(inp), None,
+                                 None, None, None, p0, None, s0,
+                                 None) == cm.CMIF_ERR_WRONG_MODE
+        gm = (ctypes.c_void_p * 1)(None)
+        assert lib.cmif_backward(ctypes.c_void_p(h1), ctypes.byref(inp),
+                                 ctypes.cast(gm, cm._PP), None, None,
+                                 ctypes.c_void_p(256), p1, ctypes.c_void_p(512),
+                                 s1, None) == cm.CMIF_ERR_INVALID_ARGUMENT
+        # compute on a SOFT plan without memberships
+        out = cm.cmif_outputs()
+        assert lib.cmif_compute(ctypes.c_void_p(h1), ctypes.byref(inp),
+                                ctypes.byref(out), ctypes.c_void_p(256), p1,
+                                ctypes.c_void_p(512), s1,
+                                None) == cm.CMIF_ERR_INVALID_ARGUMENT
+    finally:
+        cm.cmif_plan_free(h0)
+        cm.cmif_plan_free(h1)
 
 
 def test_status_strings(cm):
