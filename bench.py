@@ -17,9 +17,18 @@ The JSON line also carries:
                 counter summary in profiles/ when its source hash matches;
   cpu_baseline  the CPU oracle (direct method) on a bounded sample: one
                 angle's full map on all host threads;
-  plain_fp64    the same alignment through the plain per-angle FP64
-                schedule (one angle per pass, every count map materialised)
-                and the speed-up of the batched FP32 path over it.
+  plain_fp64    the same alignment through the library's plain FP64
+                schedule (paper-shaped: every level set, mask and
+                correlation transformed on its own, materialised FP64 maps,
+                a separate entropy kernel, host sync per angle) and the
+                speed-up of the batched FP32 path over it;
+  soft          the soft-membership batch (16 pairs, sides 128-384, Q 8):
+                forward, logsumexp(MI/0.01) over eligible shifts and the
+                library's backward, per step.
+
+--copy-gib G adds a plain device copy of G GiB (three times) after the
+measurement: rocprofv3 counter passes use it to calibrate FETCH_SIZE and
+WRITE_SIZE against bytes known to move.
 """
 
 from __future__ import annotations
@@ -82,15 +91,68 @@ def cpu_baseline(c):
                        f" direct method) in {dt:.1f} s on {nt} threads")
 
 
+def soft_bench(cm, torch, np, synth, steps):
+    """Soft batch: one step = forward MI maps of all 16 pairs, the loss
+    sum_pairs logsumexp(MI/0.01 over eligible shifts) and its gradient
+    w.r.t. every membership map through the library's adjoint."""
+    cfg = synth.config5()
+    pairs = cfg["pairs"]
+    sizes = [(*p["MA"].shape, *p["MB"].shape) for p in pairs]
+    plan = cm.Plan(sizes, cfg["q"], cfg["q"], mode="soft", precision="fp32",
+                   flags=cm.CMIF_FLAG_SAVE_FOR_BACKWARD)
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    u8 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint8)).cuda()
+    A = [f32(p["PA"]) for p in pairs]
+    B = [f32(p["PB"]) for p in pairs]
+    MA = [u8(p["MA"]) for p in pairs]
+    MB = [u8(p["MB"]) for p in pairs]
+    # eligibility (gamma 0.5 of the mask overlap) does not depend on the
+    # memberships: computed once
+    n = plan.compute(A, MA, B, MB, mi=False, n=True)["n"]
+    elig = [(nk[0] >= cfg["gamma"] * nk[0].max()) for nk in n]
+
+    def step():
+        mi = plan.compute(A, MA, B, MB, mi=True, n=False)["mi"]
+        grads, loss = [], 0.0
+        for k in range(len(pairs)):
+            m = mi[k][0].detach().requires_grad_(True)
+            lk = torch.logsumexp(m[elig[k]] / cfg["temperature"], dim=0)
+            lk.backward()
+            grads.append(m.grad[None])
+            loss += float(lk)
+        ga, gb = plan.backward(A, MA, B, MB, grads)
+        return loss, ga, gb
+
+    step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        loss, ga, gb = step()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    med = float(np.median(times))
+    return dict(ms_per_step_median=round(med, 3), pairs=len(pairs),
+                pairs_per_s=round(len(pairs) * 1000.0 / med, 2),
+                sizes=sizes, loss=loss,
+                note="wall time per forward + loss + backward step "
+                     "(host syncs included)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-angle FP64 comparator")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-soft", action="store_true",
+                    help="skip the soft-membership batch")
+    ap.add_argument("--soft-steps", type=int, default=5)
+    ap.add_argument("--copy-gib", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not "
@@ -114,27 +176,39 @@ def main():
                    gamma=c["gamma"], precision="fp32")
     n_maps = len(c["angles"])
 
-    first = plan.align(A, MA, B, MB)
+    # warm-up: the first call captures the launch graph the timed steps replay
+    plan.align(A, MA, B, MB)
     for _ in range(max(args.warmup - 1, 0)):
         plan.align(A, MA, B, MB)
     torch.cuda.synchronize()
-
-    cm.cmif_profile_read(plan.handle)          # clear
-    cm.cmif_profile_enable(plan.handle, True)
-    torch.cuda.synchronize()
+    info0 = plan.info()
     t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record()
+    for k in range(args.steps):
         out = plan.align(A, MA, B, MB, sync=False)
-    ev1.record()
+        evs[k + 1].record()
+        print(f"[bench] step {k + 1}/{args.steps} enqueued", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_total = ev0.elapsed_time(ev1)
-    cm.cmif_profile_enable(plan.handle, False)
-    stages = cm.cmif_profile_read(plan.handle)
+    ms_total = evs[0].elapsed_time(evs[-1])
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    info1 = plan.info()
+    replays = info1["graph_replays"] - info0["graph_replays"]
     ms_per_step = ms_total / args.steps
+    # stage times: the same steps launched eagerly with a HIP event pair
+    # around every launch on the library's stream (same kernels, same
+    # launch configuration as the replayed graph)
+    stage_steps = min(args.steps, 3)
+    cm.cmif_profile_read(plan.handle)          # clear
+    cm.cmif_profile_enable(plan.handle, True)
+    for _ in range(stage_steps):
+        plan.align(A, MA, B, MB, sync=False)
+    torch.cuda.synchronize()
+    stages = cm.cmif_profile_read(plan.handle)
+    cm.cmif_profile_enable(plan.handle, False)
+    eager_ms = sum(s["total_ms"] for s in stages) / stage_steps
     value = n_maps * 1000.0 / ms_per_step
     best = cm.best_from_bytes(bytes(out["best_raw"][0].cpu().numpy()))
 
@@ -153,25 +227,57 @@ def main():
 
     plain = None
     if not args.no_plain:
+        print("[bench] plain FP64 schedule", file=sys.stderr, flush=True)
         pplan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
-                        gamma=c["gamma"], precision="fp64", angle_batch=1,
-                        flags=cm.CMIF_FLAG_NO_GRAPH)
+                        gamma=c["gamma"], precision="fp64",
+                        flags=cm.CMIF_FLAG_PLAIN_SCHEDULE)
         pplan.align(A, MA, B, MB)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        pres = pplan.align(A, MA, B, MB)
-        e1.record()
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1)
+        pms = []
+        for k in range(args.plain_steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pres = pplan.align(A, MA, B, MB)
+            e1.record()
+            torch.cuda.synchronize()
+            pms.append(e0.elapsed_time(e1))
+            print(f"[bench] plain step {k + 1}: {pms[-1]:.1f} ms", file=sys.stderr,
+                  flush=True)
+        pmed = float(np.median(pms))
         pb = pres["best"][0]
-        plain = dict(ms_per_step=round(pms, 3),
-                     value=round(n_maps * 1000.0 / pms, 2), unit="maps/s",
-                     schedule="fp64 FFTs, one angle per pass, same fused kernels",
+        plain = dict(ms_per_step_median=round(pmed, 3),
+                     ms_per_step_all=[round(v, 3) for v in pms],
+                     value=round(n_maps * 1000.0 / pmed, 2), unit="maps/s",
+                     schedule="FP64; per angle 34 forward and 289 inverse "
+                              "transforms each launched alone, separate "
+                              "product and entropy kernels, materialised "
+                              "FP64 maps, host sync per angle",
                      same_best=(pb["angle_index"], pb["dy"], pb["dx"]) ==
                      (best["angle_index"], best["dy"], best["dx"]))
         del pplan
+
+    soft = None
+    if not args.no_soft:
+        print("[bench] soft batch", file=sys.stderr, flush=True)
+        soft = soft_bench(cm, torch, np, synth, args.soft_steps)
+
+    if args.copy_gib > 0:
+        # calibration copies of known size: a contiguous device copy (wide
+        # requests), then 64-byte rows out of 128-byte rows (requests of one
+        # 64-byte segment, like the library's row and tile accesses)
+        nbytes = int(args.copy_gib * (1 << 30))
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rows = src.view(-1, 128)[:, :64]
+        half = torch.empty((rows.shape[0], 64), dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            half.copy_(rows)
+        torch.cuda.synchronize()
+        del src, dst, rows, half
 
     cpu = None
     if not args.no_cpu:
@@ -200,11 +306,17 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "ms_per_step_median": round(float(np.median(step_ms)), 3),
         "plain_fp64": plain,
-        "speedup_vs_plain_fp64": (round(plain["ms_per_step"] / ms_per_step, 3)
+        "speedup_vs_plain_fp64": (round(plain["ms_per_step_median"] /
+                                        float(np.median(step_ms)), 3)
                                   if plain else None),
+        "soft": soft,
+        "graph": dict(replays=replays, captures=info1["graph_captures"],
+                      stage_steps=stage_steps,
+                      eager_kernel_ms_per_step=round(eager_ms, 3)),
         "stages": {s["name"]: dict(launches=s["launches"],
-                                   ms_per_step=round(s["total_ms"] / args.steps, 3),
+                                   ms_per_step=round(s["total_ms"] / stage_steps, 3),
                                    gbs=round(s["bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1)
                                    if s["total_ms"] > 0 else None)
                    for s in stages},

@@ -100,7 +100,16 @@ enum {
      graph capture (a debugging aid; results are identical) */
   CMIF_FLAG_NO_GRAPH = 1u << 1,
   /* SOFT: keep what cmif_backward needs in the persistent workspace */
-  CMIF_FLAG_SAVE_FOR_BACKWARD = 1u << 2
+  CMIF_FLAG_SAVE_FOR_BACKWARD = 1u << 2,
+  /* HARD + FP64 only: the paper-shaped schedule (Sec. 3.2, Eq. 15 transform
+     count), kept as the comparator for the fused path: per angle, every
+     level set and mask of A and B transformed on its own, then for each of
+     the 1 + Q_A + Q_B + Q_A*Q_B correlations (Eq. 9-11) a product kernel, a
+     column and a row inverse transform writing the real map to memory, one
+     entropy kernel over all maps, and a host synchronisation before the next
+     angle.  Same results; emits mi, n, best and per_angle (counts and
+     digests are rejected) */
+  CMIF_FLAG_PLAIN_SCHEDULE = 1u << 3
 };
 
 /* Plan description.  Every pointer is a host pointer read during cmif_plan
@@ -203,7 +212,15 @@ void cmif_plan_free(cmif_plan_t plan);
 cmif_status cmif_workspace_size(cmif_plan_t plan, size_t* persistent,
                                 size_t* scratch);
 
-/* CMIF maps (Eq. 5, Sec. 3.2) for every image pair and angle, plus the
+/* Launch sequence: unless the plan has CMIF_FLAG_NO_GRAPH (or the plain
+   schedule, or stage profiling is on), cmif_compute and cmif_align record
+   their whole launch sequence into a HIP graph on a private stream the first
+   time and launch the graph on `stream`; later calls with the same device
+   pointers (inputs, outputs, workspace, stream) replay it, new pointers
+   capture again.  Results are identical either way; the contents behind the
+   pointers may change freely between calls.
+
+   CMIF maps (Eq. 5, Sec. 3.2) for every image pair and angle, plus the
    Alg. 1 results when out->best / out->per_angle are given.  Any output may
    be NULL.  HARD plans read labels/masks, SOFT plans memberships/masks (and
    ignore n, counts and digest). */
@@ -239,7 +256,10 @@ cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
    algorithmic HBM bytes of those launches (the bytes the stage must move at
    minimum: its inputs read once and its outputs written once), then clears
    the records.  Stages: "check_labels", "fwd_rows", "fwd_cols",
-   "pair_cols", "pair_rows", "pair_counts", "argmax", "fill", "tables".
+   "pair_cols", "pair_rows", "pair_counts", "argmax", "fill", "tables",
+   "fb_list", "fb_forward", "fb_pairs", "fb_rows" (FP64 re-run), "soft_grad"
+   (adjoint), "plain" (plain schedule).  While profiling is enabled the
+   calls launch eagerly (no graph).
    Disabled by default; enabling costs two event records per launch. */
 typedef struct cmif_stage_time {
   char name[24];
@@ -255,6 +275,19 @@ cmif_status cmif_profile_enable(cmif_plan_t plan, int32_t enable);
    *count. */
 cmif_status cmif_profile_read(cmif_plan_t plan, cmif_stage_time* out,
                               int32_t capacity, int32_t* count);
+
+/* What a plan chose, and how its calls ran so far. */
+typedef struct cmif_plan_info {
+  int32_t angle_batch;        /* angles per pipeline pass */
+  int32_t fallback_capacity;  /* FP64 re-run slots per pass (0: none) */
+  int32_t graph_captures;     /* launch sequences captured into HIP graphs */
+  int32_t graph_replays;      /* calls that replayed a captured graph */
+  int32_t fft_h, fft_w;       /* FFT lengths of image pair 0 */
+  int32_t reserved[2];
+} cmif_plan_info;
+
+/* Fills *info (host memory).  Errors: CMIF_ERR_INVALID_ARGUMENT on NULL. */
+cmif_status cmif_plan_query(cmif_plan_t plan, cmif_plan_info* info);
 
 /* Static description of a status code. */
 const char* cmif_status_string(cmif_status status);

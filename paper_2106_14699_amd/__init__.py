@@ -36,10 +36,11 @@ CMIF_MODE_SOFT = 1
 CMIF_FLAG_FORCE_FALLBACK = 1 << 0
 CMIF_FLAG_NO_GRAPH = 1 << 1
 CMIF_FLAG_SAVE_FOR_BACKWARD = 1 << 2
+CMIF_FLAG_PLAIN_SCHEDULE = 1 << 3
 
 EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_compute", "cmif_align", "cmif_backward",
-            "cmif_profile_enable", "cmif_profile_read",
+            "cmif_profile_enable", "cmif_profile_read", "cmif_plan_query",
             "cmif_status_string", "cmif_last_error")
 
 _P = ctypes.c_void_p
@@ -89,6 +90,15 @@ class cmif_outputs(ctypes.Structure):
                 ("best", _P), ("per_angle", _P), ("stats", _P)]
 
 
+class cmif_plan_info(ctypes.Structure):
+    _fields_ = [("angle_batch", ctypes.c_int32),
+                ("fallback_capacity", ctypes.c_int32),
+                ("graph_captures", ctypes.c_int32),
+                ("graph_replays", ctypes.c_int32),
+                ("fft_h", ctypes.c_int32), ("fft_w", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
 class cmif_stage_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("total_ms", ctypes.c_double),
@@ -126,6 +136,8 @@ def _load_lib():
     lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
                                   _PP, _P, S, _P, S, _P]
     lib.cmif_backward.restype = ctypes.c_int
+    lib.cmif_plan_query.argtypes = [_P, ctypes.POINTER(cmif_plan_info)]
+    lib.cmif_plan_query.restype = ctypes.c_int
     lib.cmif_profile_enable.argtypes = [_P, ctypes.c_int32]
     lib.cmif_profile_enable.restype = ctypes.c_int
     lib.cmif_profile_read.argtypes = [_P, ctypes.POINTER(cmif_stage_time),
@@ -197,6 +209,13 @@ def cmif_backward(plan, inputs, grad_mi, grad_a, grad_b, persistent,
                               grad_b, _P(persistent), persistent_bytes,
                               _P(scratch), scratch_bytes, _P(stream)),
            "cmif_backward")
+
+
+def cmif_plan_query(plan: int) -> dict:
+    info = cmif_plan_info()
+    _check(_lib.cmif_plan_query(_P(plan), ctypes.byref(info)), "cmif_plan_query")
+    return {k: getattr(info, k) for k, _ in cmif_plan_info._fields_
+            if k != "reserved"}
 
 
 def cmif_profile_enable(plan: int, enable: bool) -> None:
@@ -341,13 +360,30 @@ class Plan:
     def _stream(self):
         return self._torch.cuda.current_stream(self.device).cuda_stream
 
+    def _buffer(self, reuse, key, shape, dtype):
+        """Output tensor: fresh, or (reuse=True) kept by the plan so that
+        repeated calls pass the same pointers and replay the captured
+        launch graph (the returned tensor is overwritten by the next call)."""
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        if not reuse:
+            return torch.empty(shape, dtype=dtype, device=dev)
+        cache = self.__dict__.setdefault("_bufs", {})
+        t = cache.get(key)
+        if t is None or tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+            t = torch.empty(shape, dtype=dtype, device=dev)
+            cache[key] = t
+        return t
+
     def compute(self, A, MA=None, B=None, MB=None, *, mi=True, n=True,
-                counts=False, digest=False, best=False, per_angle=False):
+                counts=False, digest=False, best=False, per_angle=False,
+                reuse=False):
         """CMIF maps for every pair and angle.  Returns a dict of lists (one
-        entry per pair) of torch tensors, plus 'stats' (dict)."""
+        entry per pair) of torch tensors, plus 'stats' (dict).  With
+        reuse=True the output tensors belong to the plan and are overwritten
+        by its next call (stable pointers replay the captured graph)."""
         torch = self._torch
         inp, keep = self._inputs(A, MA, B, MB)
-        dev = f"cuda:{self.device}"
         na = len(self.angles)
         res = {}
         outs = cmif_outputs()
@@ -359,19 +395,21 @@ class Plan:
                 ("digest", digest, torch.int64,
                  lambda s: (na, self.q_a, self.q_b))):
             if want:
-                ts = [torch.empty(shape_fn(self.map_shape(p)), dtype=dtype,
-                                  device=dev) for p in range(len(self.sizes))]
+                ts = [self._buffer(reuse, ("c", name, p),
+                                   shape_fn(self.map_shape(p)), dtype)
+                      for p in range(len(self.sizes))]
                 res[name] = ts
                 pa, arr = _ptr_array([t.data_ptr() for t in ts])
                 keep.append(arr)
                 setattr(outs, name, pa)
         nbest = ctypes.sizeof(cmif_best)
-        best_t = torch.empty((len(self.sizes), nbest), dtype=torch.uint8,
-                             device=dev) if best else None
-        pa_t = torch.empty((len(self.sizes), na, nbest), dtype=torch.uint8,
-                           device=dev) if per_angle else None
-        stats_t = torch.zeros(ctypes.sizeof(cmif_stats), dtype=torch.uint8,
-                              device=dev)
+        best_t = self._buffer(reuse, ("c", "best"), (len(self.sizes), nbest),
+                              torch.uint8) if best else None
+        pa_t = self._buffer(reuse, ("c", "pa"), (len(self.sizes), na, nbest),
+                            torch.uint8) if per_angle else None
+        stats_t = self._buffer(reuse, ("c", "stats"),
+                               (ctypes.sizeof(cmif_stats),), torch.uint8)
+        stats_t.zero_()
         outs.best = best_t.data_ptr() if best else None
         outs.per_angle = pa_t.data_ptr() if per_angle else None
         outs.stats = stats_t.data_ptr()
@@ -391,21 +429,27 @@ class Plan:
         del keep
         return res
 
+    def info(self) -> dict:
+        return cmif_plan_query(self.handle)
+
     def align(self, A, MA=None, B=None, MB=None, *, per_angle=False,
               sync=True):
         """Alg. 1 over the plan's angles for every pair.  Returns a list of
-        best dicts (and per-angle lists), plus stats."""
+        best dicts (and per-angle lists), plus stats.  The small result
+        buffers belong to the plan (stable pointers replay the captured
+        graph): with sync=False the returned raw tensors are overwritten by
+        the next call."""
         torch = self._torch
         inp, keep = self._inputs(A, MA, B, MB)
-        dev = f"cuda:{self.device}"
         na = len(self.angles)
         nbest = ctypes.sizeof(cmif_best)
-        best_t = torch.empty((len(self.sizes), nbest), dtype=torch.uint8,
-                             device=dev)
-        pa_t = torch.empty((len(self.sizes), na, nbest), dtype=torch.uint8,
-                           device=dev) if per_angle else None
-        stats_t = torch.zeros(ctypes.sizeof(cmif_stats), dtype=torch.uint8,
-                              device=dev)
+        best_t = self._buffer(True, ("a", "best"), (len(self.sizes), nbest),
+                              torch.uint8)
+        pa_t = self._buffer(True, ("a", "pa"), (len(self.sizes), na, nbest),
+                            torch.uint8) if per_angle else None
+        stats_t = self._buffer(True, ("a", "stats"),
+                               (ctypes.sizeof(cmif_stats),), torch.uint8)
+        stats_t.zero_()
         pb, pp, sb, sp = self.workspace()
         cmif_align(self.handle, inp, best_t.data_ptr(),
                    pa_t.data_ptr() if per_angle else None, stats_t.data_ptr(),

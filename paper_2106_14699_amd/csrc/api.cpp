@@ -55,18 +55,21 @@ struct ScratchLayout {
   size_t xa64, fa64, xb64, fb64, z64, cnt64, items, n_items, ovr, gate;
   // SOFT: FP64 mask-overlap pass (one "label" per image) and the adjoint
   size_t ov_xa, ov_fa, ov_xb, ov_fb, ov_z, zg, gh, gxa, gxb;
+  // plain schedule: one row-spectrum buffer, Q_A+1 and Q_B+1 2D spectra, the
+  // product, one pair's columns and all 1+Q_A+Q_B+Q_A*Q_B real maps
+  size_t pl_x, pl_fa, pl_fb, pl_y, pl_z, pl_maps;
   size_t end;
 };
 
 enum Stage {
   ST_CHECK, ST_FWD_ROWS, ST_FWD_COLS, ST_PAIR_COLS, ST_PAIR_ROWS,
   ST_PAIR_COUNTS, ST_ARGMAX, ST_FILL, ST_TABLES, ST_FB_LIST, ST_FB_FWD,
-  ST_FB_PAIR, ST_FB_ROWS, ST_SOFT_GRAD, ST_COUNT
+  ST_FB_PAIR, ST_FB_ROWS, ST_SOFT_GRAD, ST_PLAIN, ST_COUNT
 };
 const char* const kStageNames[ST_COUNT] = {
     "check_labels", "fwd_rows", "fwd_cols", "pair_cols", "pair_rows",
     "pair_counts", "argmax", "fill", "tables", "fb_list", "fb_forward",
-    "fb_pairs", "fb_rows", "soft_grad"};
+    "fb_pairs", "fb_rows", "soft_grad", "plain"};
 
 struct ProfRec {
   int stage;
@@ -92,6 +95,25 @@ struct Profiler {
   }
 };
 
+// One captured launch sequence, replayed while the call's pointers repeat.
+struct GraphCache {
+  bool valid = false;
+  bool refused = false;      // the runtime refused a capture: stay eager
+  std::vector<uintptr_t> key;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;  // private capture stream (default priority)
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    valid = false;
+    key.clear();
+  }
+  ~GraphCache() {
+    reset();
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
 }  // namespace
 
 struct cmif_plan_s {
@@ -112,6 +134,9 @@ struct cmif_plan_s {
   int nchunks_max = 1;
   bool device_checked = false;
   Profiler prof;
+  GraphCache graphs[2];  // [0] cmif_compute, [1] cmif_align
+  int graph_captures = 0;
+  int graph_replays = 0;
 };
 
 namespace {
@@ -154,6 +179,15 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
     L.n_items = take(sizeof(uint32_t));
     L.ovr = take(nb * qa * qb * sizeof(int32_t));
     L.gate = take((nb + 1) * sizeof(uint32_t));
+  }
+  if (P.d.flags & CMIF_FLAG_PLAIN_SCHEDULE) {
+    const size_t E64 = sizeof(double2);
+    L.pl_x = take(half * std::max(g.ha, g.hb) * E64);
+    L.pl_fa = take((qa + 1) * half * g.ph * E64);
+    L.pl_fb = take((qb + 1) * half * g.ph * E64);
+    L.pl_y = take(half * g.ph * E64);
+    L.pl_z = take(half * g.sh * E64);
+    L.pl_maps = take((1 + qa + qb + qa * qb) * (size_t)g.sh * g.sw * sizeof(double));
   }
   if (P.d.mode == CMIF_MODE_SOFT) {
     const size_t E64 = sizeof(double2);
@@ -274,12 +308,13 @@ cmif_status forward(cmif_plan_s& P, hipStream_t st, int stage_rows,
                      int H, int W, int Q, int nb, const int32_t* rc,
                      const int32_t* rs, const PairPlan& g, const uint8_t* pers,
                      C2<T>* x, C2<T>* f, const uint32_t* gate,
-                     const float* memb = nullptr, cmif_stats* stats = nullptr) {
+                     const float* memb = nullptr, cmif_stats* stats = nullptr,
+                     int label0 = 0) {
   using CT = C2<T>;
   const int half = g.pw / 2;
   FwdRowsArgs<T> r{};
   r.lab = lab; r.msk = msk; r.memb = memb; r.stats = stats;
-  r.H = H; r.W = W; r.Q = Q; r.nb = nb;
+  r.H = H; r.W = W; r.Q = Q; r.nb = nb; r.label0 = label0;
   for (int b = 0; b < nb; ++b) { r.rot.c[b] = rc[b]; r.rot.s[b] = rs[b]; }
   r.xrow = x; r.angle_stride = (long long)Q * half * H;
   r.tw = twiddles<T>(P, pers, g.pw); r.gate = gate;
@@ -561,6 +596,137 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
   return CMIF_OK;
 }
 
+// The paper-shaped comparator (CMIF_FLAG_PLAIN_SCHEDULE): per angle, each
+// of the Q_A + Q_B + 2 forward transforms (level sets and masks, Eq. 8) and
+// each of the 1 + Q_A + Q_B + Q_A Q_B correlations (Eq. 9-11) runs as its own
+// launches (product, column inverse, row inverse writing the real map), then
+// one entropy kernel reads every map (Eq. 12) and the host waits for the
+// angle before starting the next.
+cmif_status run_pair_plain(cmif_plan_s& P, int p, const uint8_t* la,
+                           const uint8_t* ma, const uint8_t* lb,
+                           const uint8_t* mb, const CallOutputs& o,
+                           uint8_t* pers, uint8_t* scr, hipStream_t st) {
+  using C64 = C2<double>;
+  const PairPlan& g = P.pairs[p];
+  const ScratchLayout L = layout_for(P, g);
+  const int qa = P.d.q_a, qb = P.d.q_b;
+  const int half = g.pw / 2;
+  const long long S = (long long)g.sh * g.sw;
+  const long long fstride = (long long)half * g.ph;
+  C64* x = reinterpret_cast<C64*>(scr + L.pl_x);
+  C64* fa = reinterpret_cast<C64*>(scr + L.pl_fa);  // [qa] level sets, [qa] = mask
+  C64* fb = reinterpret_cast<C64*>(scr + L.pl_fb);
+  C64* y = reinterpret_cast<C64*>(scr + L.pl_y);
+  C64* z = reinterpret_cast<C64*>(scr + L.pl_z);
+  double* maps = reinterpret_cast<double*>(scr + L.pl_maps);
+  double* joint = maps;                        // [qa*qb][S]
+  double* marg_a = maps + (long long)qa * qb * S;
+  double* marg_b = marg_a + (long long)qa * S;
+  double* nmap = marg_b + (long long)qb * S;
+  double* mi_s = reinterpret_cast<double*>(scr + L.mi);
+  int32_t* n_s = reinterpret_cast<int32_t*>(scr + L.n);
+  uint32_t* maxn = reinterpret_cast<uint32_t*>(scr + L.maxn);
+  ArgPartial* partial = reinterpret_cast<ArgPartial*>(scr + L.partial);
+  cmif_best* running = reinterpret_cast<cmif_best*>(scr + L.running);
+  const int32_t id_c = 65536, id_s = 0;
+  const int nang = (int)P.angles.size();
+  const int rpc = rows_per_chunk(g.sh);
+  const int nchunks = (g.sh + rpc - 1) / rpc;
+  const bool want_best = o.best != nullptr || o.per_angle != nullptr;
+  if (o.stats) {
+    STAGE(ST_CHECK, 2.0 * g.ha * g.wa,
+          launch_check_labels(la, ma, (long long)g.ha * g.wa, qa, o.stats, st));
+    STAGE(ST_CHECK, 2.0 * g.hb * g.wb,
+          launch_check_labels(lb, mb, (long long)g.hb * g.wb, qb, o.stats, st));
+  }
+  // one correlation: product, column inverse, row inverse -> real map
+  auto correlate = [&](const C64* f1, const C64* f2, double* out) -> cmif_status {
+    STAGE(ST_PLAIN, 3.0 * fstride * sizeof(C64),
+          launch_plain_product(f1, f2, y, half, g.ph, st));
+    PairColsArgs<double> pc{};
+    pc.FA = nullptr; pc.FB = y; pc.fb_angle_stride = 0; pc.fb_label_stride = fstride;
+    pc.QA = 1; pc.QB = 1; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+    pc.tiles = half / tile_width<double>(); pc.nb = 1; pc.Z = z;
+    pc.z_angle_stride = 0; pc.z_pair_stride = (long long)half * g.sh;
+    pc.tw = twiddles<double>(P, pers, g.ph);
+    STAGE(ST_PLAIN, ((double)fstride + (double)half * g.sh) * sizeof(C64),
+          launch_pair_cols<double>(g.ph, pc, st));
+    PairCountsArgs<double> pk{};
+    pk.Z = z; pk.z_angle_stride = 0; pk.z_pair_stride = pc.z_pair_stride;
+    pk.QA = 1; pk.QB = 1; pk.wa = g.wa; pk.wb = g.wb; pk.sh = g.sh; pk.sw = g.sw;
+    pk.ph = g.ph; pk.nb = 1; pk.tw = twiddles<double>(P, pers, g.pw);
+    pk.values = out; pk.counts_angle_stride = S;
+    STAGE(ST_PLAIN, (double)half * g.sh * sizeof(C64) + 8.0 * S,
+          launch_pair_counts<double>(g.pw, pk, st));
+    return CMIF_OK;
+  };
+  for (int ang = 0; ang < nang; ++ang) {
+    cmif_status s;
+    // forward transforms, one level set (or mask) per launch pair
+    for (int a = 0; a <= qa; ++a) {
+      s = forward<double>(P, st, ST_PLAIN, ST_PLAIN, a < qa ? la : nullptr, ma,
+                          g.ha, g.wa, 1, 1, &id_c, &id_s, g, pers, x,
+                          fa + a * fstride, nullptr, nullptr, nullptr,
+                          a < qa ? a : 0);
+      if (s != CMIF_OK) return s;
+    }
+    for (int b = 0; b <= qb; ++b) {
+      s = forward<double>(P, st, ST_PLAIN, ST_PLAIN, b < qb ? lb : nullptr, mb,
+                          g.hb, g.wb, 1, 1, &P.rc[ang], &P.rs[ang], g, pers, x,
+                          fb + b * fstride, nullptr, nullptr, nullptr,
+                          b < qb ? b : 0);
+      if (s != CMIF_OK) return s;
+    }
+    // Eq. 9: joint; Eq. 10: marginals (level set against the other mask);
+    // Eq. 11: N (mask against mask)
+    for (int a = 0; a < qa; ++a)
+      for (int b = 0; b < qb; ++b) {
+        s = correlate(fa + a * fstride, fb + b * fstride, joint + (long long)(a * qb + b) * S);
+        if (s != CMIF_OK) return s;
+      }
+    for (int a = 0; a < qa; ++a) {
+      s = correlate(fa + a * fstride, fb + qb * fstride, marg_a + a * S);
+      if (s != CMIF_OK) return s;
+    }
+    for (int b = 0; b < qb; ++b) {
+      s = correlate(fa + qa * fstride, fb + b * fstride, marg_b + b * S);
+      if (s != CMIF_OK) return s;
+    }
+    s = correlate(fa + qa * fstride, fb + qb * fstride, nmap);
+    if (s != CMIF_OK) return s;
+    STAGE(ST_FILL, 4.0, launch_fill_u32(maxn, 0u, 1, st));
+    double* mi_ptr = o.mi ? o.mi + ang * S : mi_s;
+    int32_t* n_ptr = o.n ? o.n + ang * S : n_s;
+    PlainEntropyArgs pe{};
+    pe.joint = joint; pe.marg_a = marg_a; pe.marg_b = marg_b; pe.nmap = nmap;
+    pe.S = S; pe.QA = qa; pe.QB = qb; pe.mi = mi_ptr; pe.n = n_ptr; pe.maxn = maxn;
+    STAGE(ST_PLAIN, 8.0 * S * (1 + qa + qb + qa * qb) + 12.0 * S,
+          launch_plain_entropy(pe, st));
+    if (want_best) {
+      ArgmaxArgs am{};
+      am.mi = mi_ptr; am.n = n_ptr; am.angle_stride = S; am.maxn = maxn;
+      am.sh = g.sh; am.sw = g.sw; am.nb = 1; am.rows_per_chunk = rpc;
+      am.nchunks = nchunks; am.gamma = P.d.gamma; am.partial = partial;
+      STAGE(ST_ARGMAX, 12.0 * S, launch_argmax(am, st));
+      ArgmaxFinalArgs af{};
+      af.partial = partial; af.nb = 1; af.nchunks = nchunks; af.sw = g.sw;
+      af.ha = g.ha; af.wa = g.wa; af.angle0 = ang;
+      af.angles[0] = P.angles[ang];
+      af.per_angle = o.per_angle; af.running = running;
+      af.first_batch = ang == 0; af.best_out = o.best;
+      af.last_batch = ang + 1 >= nang;
+      STAGE(ST_ARGMAX, (double)nchunks * sizeof(ArgPartial),
+            launch_argmax_final(af, st));
+    }
+    // the host waits for every angle before it starts the next
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, std::string("hipStreamSynchronize: ") +
+                                       hipGetErrorString(e));
+  }
+  return CMIF_OK;
+}
+
 cmif_status validate_ws(const cmif_plan_s* P, void* pers, size_t pers_bytes,
                         void* scr, size_t scr_bytes) {
   if (pers_bytes < P->persistent_bytes || scr_bytes < P->scratch_bytes)
@@ -622,6 +788,10 @@ cmif_status run_calls(cmif_plan_s* P, const cmif_inputs* in,
   if (s != CMIF_OK) return s;
   uint8_t* pb = static_cast<uint8_t*>(pers);
   uint8_t* sb = static_cast<uint8_t*>(scr);
+  if ((P->d.flags & CMIF_FLAG_PLAIN_SCHEDULE) && out &&
+      (out->counts || out->digest))
+    return fail(CMIF_ERR_INVALID_ARGUMENT,
+                "the plain schedule emits mi, n, best and per_angle only");
   s = init_tables(P, pb, st);
   if (s != CMIF_OK) return s;
   cmif_plan_s& PP = *P;
@@ -655,7 +825,9 @@ cmif_status run_calls(cmif_plan_s* P, const cmif_inputs* in,
     const uint8_t* lb = soft ? nullptr : in->labels_b[p];
     const float* pa = soft ? in->memb_a[p] : nullptr;
     const float* pbm = soft ? in->memb_b[p] : nullptr;
-    if (P->d.precision == CMIF_PREC_FP64)
+    if (P->d.flags & CMIF_FLAG_PLAIN_SCHEDULE)
+      s = run_pair_plain(*P, p, la, ma, lb, mb, o, pb, sb, st);
+    else if (P->d.precision == CMIF_PREC_FP64)
       s = run_pair<double>(*P, p, la, ma, lb, mb, pa, pbm, o, pb, sb, st);
     else
       s = run_pair<float>(*P, p, la, ma, lb, mb, pa, pbm, o, pb, sb, st);
@@ -751,6 +923,104 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
   return CMIF_OK;
 }
 
+// Stage profiling brackets every launch with events on the stream, so it
+// launches eagerly.
+bool graph_allowed(const cmif_plan_s* P) {
+  return !(P->d.flags & (CMIF_FLAG_NO_GRAPH | CMIF_FLAG_PLAIN_SCHEDULE)) &&
+         !P->prof.on;
+}
+
+void key_ptrs(std::vector<uintptr_t>& k, const void* const* arr, int n) {
+  k.push_back(arr ? 1u : 0u);
+  if (arr)
+    for (int p = 0; p < n; ++p) k.push_back(reinterpret_cast<uintptr_t>(arr[p]));
+}
+
+std::vector<uintptr_t> call_key(const cmif_plan_s* P, int op,
+                                const cmif_inputs* in, const cmif_outputs* out,
+                                const void* best, const void* per_angle,
+                                const void* stats, const void* pers,
+                                const void* scr, hipStream_t st) {
+  const int n = P->d.n_pairs;
+  std::vector<uintptr_t> k;
+  k.push_back((uintptr_t)op);
+  key_ptrs(k, reinterpret_cast<const void* const*>(in->labels_a), n);
+  key_ptrs(k, reinterpret_cast<const void* const*>(in->mask_a), n);
+  key_ptrs(k, reinterpret_cast<const void* const*>(in->labels_b), n);
+  key_ptrs(k, reinterpret_cast<const void* const*>(in->mask_b), n);
+  key_ptrs(k, reinterpret_cast<const void* const*>(in->memb_a), n);
+  key_ptrs(k, reinterpret_cast<const void* const*>(in->memb_b), n);
+  if (out) {
+    key_ptrs(k, reinterpret_cast<const void* const*>(out->mi), n);
+    key_ptrs(k, reinterpret_cast<const void* const*>(out->n), n);
+    key_ptrs(k, reinterpret_cast<const void* const*>(out->counts), n);
+    key_ptrs(k, reinterpret_cast<const void* const*>(out->digest), n);
+  }
+  for (const void* p : {best, per_angle, stats, pers, scr, (const void*)st})
+    k.push_back(reinterpret_cast<uintptr_t>(p));
+  return k;
+}
+
+// Runs `body` through a captured graph: replays the cached one when the
+// call's pointers match, otherwise captures the launch sequence on a
+// private stream, instantiates it and launches it on `st` (ordered after the
+// caller's earlier work on `st`).  A capture the runtime refuses falls back
+// to launching eagerly on `st`.
+template <class F>
+cmif_status run_graph(cmif_plan_s* P, int op, std::vector<uintptr_t> key,
+                      hipStream_t st, F&& body) {
+  GraphCache& G = P->graphs[op];
+  if (G.refused) return body(st);
+  if (G.valid && G.key == key) {
+    const hipError_t e = hipGraphLaunch(G.exec, st);
+    if (e != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    ++P->graph_replays;
+    return CMIF_OK;
+  }
+  G.reset();
+  if (!G.cs && hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking) != hipSuccess) {
+    G.cs = nullptr;
+    G.refused = true;
+    return body(st);
+  }
+  if (hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    G.refused = true;
+    return body(st);
+  }
+  const cmif_status s = body(G.cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(G.cs, &graph);
+  if (s != CMIF_OK || e != hipSuccess || graph == nullptr) {
+    // the runtime refused part of the sequence under capture: launch
+    // eagerly from now on (a genuine launch error shows up there too)
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    G.reset();
+    G.refused = true;
+    g_err.clear();
+    return body(st);
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    (void)hipGetLastError();
+    G.reset();
+    G.refused = true;
+    return body(st);
+  }
+  G.exec = exec;
+  G.key = std::move(key);
+  G.valid = true;
+  ++P->graph_captures;
+  const hipError_t el = hipGraphLaunch(G.exec, st);
+  if (el != hipSuccess)
+    return fail(CMIF_ERR_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(el));
+  return CMIF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -770,6 +1040,19 @@ const char* cmif_status_string(cmif_status s) {
 }
 
 const char* cmif_last_error(void) { return g_err.c_str(); }
+
+cmif_status cmif_plan_query(cmif_plan_t plan, cmif_plan_info* info) {
+  g_err.clear();
+  if (!plan || !info) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->angle_batch = plan->batch;
+  info->fallback_capacity = plan->fb_cap;
+  info->graph_captures = plan->graph_captures;
+  info->graph_replays = plan->graph_replays;
+  info->fft_h = plan->pairs[0].ph;
+  info->fft_w = plan->pairs[0].pw;
+  return CMIF_OK;
+}
 
 cmif_status cmif_profile_enable(cmif_plan_t plan, int32_t enable) {
   g_err.clear();
@@ -827,8 +1110,11 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   if (d->mode != CMIF_MODE_HARD && d->mode != CMIF_MODE_SOFT)
     return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown mode");
   const uint32_t known = CMIF_FLAG_FORCE_FALLBACK | CMIF_FLAG_NO_GRAPH |
-                         CMIF_FLAG_SAVE_FOR_BACKWARD;
+                         CMIF_FLAG_SAVE_FOR_BACKWARD | CMIF_FLAG_PLAIN_SCHEDULE;
   if (d->flags & ~known) return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown flags");
+  if ((d->flags & CMIF_FLAG_PLAIN_SCHEDULE) &&
+      (d->mode != CMIF_MODE_HARD || d->precision != CMIF_PREC_FP64))
+    return fail(CMIF_ERR_UNSUPPORTED, "the plain schedule is HARD and FP64 only");
   if (d->n_angles < 1)
     return fail(CMIF_ERR_INVALID_ARGUMENT, "n_angles must be >= 1");
   if (d->angles_rad == nullptr && d->n_angles != 1)
@@ -907,6 +1193,7 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   }
   batch = std::min(batch, kMaxBatch);
   batch = std::min(batch, d->n_angles);
+  if (d->flags & CMIF_FLAG_PLAIN_SCHEDULE) batch = 1;
   P->batch = std::max(batch, 1);
   if (d->precision == CMIF_PREC_FP32_ROUNDED && d->mode == CMIF_MODE_HARD) {
     const int per_pass = P->batch * d->q_a * d->q_b;
@@ -965,9 +1252,18 @@ cmif_status cmif_compute(cmif_plan_t plan, const cmif_inputs* in,
   if (s != CMIF_OK) return s;
   DeviceGuard dg(plan->d.device);
   if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
-  return run_calls(plan, in, out, out ? out->best : nullptr,
-                  out ? out->per_angle : nullptr, out ? out->stats : nullptr,
-                  persistent, scratch, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cmif_best* best = out ? out->best : nullptr;
+  cmif_best* per_angle = out ? out->per_angle : nullptr;
+  cmif_stats* stats = out ? out->stats : nullptr;
+  auto body = [&](hipStream_t s) {
+    return run_calls(plan, in, out, best, per_angle, stats, persistent, scratch, s);
+  };
+  if (!graph_allowed(plan)) return body(st);
+  return run_graph(plan, 0,
+                   call_key(plan, 0, in, out, best, per_angle, stats, persistent,
+                            scratch, st),
+                   st, body);
 }
 
 cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
@@ -987,8 +1283,16 @@ cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
   if (s != CMIF_OK) return s;
   DeviceGuard dg(plan->d.device);
   if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
-  return run_calls(plan, in, nullptr, best, per_angle, stats, persistent,
-                  scratch, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto body = [&](hipStream_t s) {
+    return run_calls(plan, in, nullptr, best, per_angle, stats, persistent,
+                     scratch, s);
+  };
+  if (!graph_allowed(plan)) return body(st);
+  return run_graph(plan, 1,
+                   call_key(plan, 1, in, nullptr, best, per_angle, stats,
+                            persistent, scratch, st),
+                   st, body);
 }
 
 cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,

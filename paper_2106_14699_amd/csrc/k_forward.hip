@@ -29,7 +29,8 @@ __device__ __forceinline__ int floordiv_pos_pow2(long long a, int shift) {
 template <typename T, int P, int TEAM>
 __global__ void __launch_bounds__(4 * TEAM)
 k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
-           const float* __restrict__ memb, int H, int W, int Q, RotArgs rot,
+           const float* __restrict__ memb, int H, int W, int Q, int label0,
+           RotArgs rot,
            C2<T>* __restrict__ xrow, long long angle_stride,
            const C2<T>* __restrict__ tw, const uint32_t* __restrict__ gate,
            cmif_stats* __restrict__ stats) {
@@ -72,9 +73,10 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
     srci[q] = si;
     uint8_t l = 255;
     if (memb == nullptr && si >= 0) {
-      // no label image: every in-mask pixel is label 0 (mask overlap counts)
-      const uint8_t v = lab ? lab[si] : (uint8_t)0;
-      if (v < Q) l = v;
+      // no label image: every in-mask pixel is label 0 (mask overlap counts);
+      // labels label0 .. label0+Q-1 become level sets 0 .. Q-1
+      const int v = lab ? (int)lab[si] : 0;
+      if (v >= label0 && v < label0 + Q) l = (uint8_t)(v - label0);
     }
     lv[q] = l;
   }
@@ -213,8 +215,8 @@ static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
   if (e != hipSuccess) return e;
   dim3 grid(a.H, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.lab, a.msk,
-                     a.memb, a.H, a.W, a.Q, a.rot, a.xrow, a.angle_stride, a.tw,
-                     a.gate, a.stats);
+                     a.memb, a.H, a.W, a.Q, a.label0, a.rot, a.xrow,
+                     a.angle_stride, a.tw, a.gate, a.stats);
   return hipGetLastError();
 }
 

@@ -205,6 +205,90 @@ hipError_t launch_fb_list(const FbListArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Plain schedule (the paper-shaped comparator): Y = conj(F_a) F_b as its
+// own kernel, element (c, k_y) per thread.  Column 0 packs the k_x = 0 and
+// k_x = P_w/2 columns (both Hermitian in k_y): they are separated, multiplied
+// and packed again, as the fused pair kernel does.
+__global__ void k_plain_product(const double2* __restrict__ fa,
+                                const double2* __restrict__ fb,
+                                double2* __restrict__ y, int half, int ph) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)half * ph) return;
+  const int c = (int)(e / ph), k = (int)(e % ph);
+  const double2 a = fa[e], b = fb[e];
+  if (c != 0) {
+    y[e] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+    return;
+  }
+  const int km = (ph - k) & (ph - 1);
+  const double2 am = fa[km], bm = fb[km];
+  // separate W = G0 + i G1 (G0, G1 Hermitian): G0 = (W + conj(Wm))/2,
+  // G1 = (W - conj(Wm))/(2i)
+  const double2 a0 = make_double2((a.x + am.x) * 0.5, (a.y - am.y) * 0.5);
+  const double2 a1 = make_double2((a.y + am.y) * 0.5, (am.x - a.x) * 0.5);
+  const double2 b0 = make_double2((b.x + bm.x) * 0.5, (b.y - bm.y) * 0.5);
+  const double2 b1 = make_double2((b.y + bm.y) * 0.5, (bm.x - b.x) * 0.5);
+  const double2 y0 = make_double2(a0.x * b0.x + a0.y * b0.y, a0.x * b0.y - a0.y * b0.x);
+  const double2 y1 = make_double2(a1.x * b1.x + a1.y * b1.y, a1.x * b1.y - a1.y * b1.x);
+  y[e] = make_double2(y0.x - y1.y, y0.y + y1.x);
+}
+
+hipError_t launch_plain_product(const C2<double>* fa, const C2<double>* fb,
+                                C2<double>* y, int half, int ph, hipStream_t st) {
+  const long long n = (long long)half * ph;
+  hipLaunchKernelGGL(k_plain_product, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                     0, st, reinterpret_cast<const double2*>(fa),
+                     reinterpret_cast<const double2*>(fb),
+                     reinterpret_cast<double2*>(y), half, ph);
+  return hipGetLastError();
+}
+
+// Plain schedule: Eq. 12 per displacement from separately transformed and
+// materialised maps (joint, both marginals, N; Eq. 9-11), each rounded to
+// the nearest integer (Sec. 3.2).  One thread per displacement.
+__device__ __forceinline__ double plain_xlog(double v) {
+  const double c = fmax(rint(v), 0.0);
+  return c > 1.0 ? c * log2(c) : 0.0;
+}
+
+__global__ void k_plain_entropy(const double* __restrict__ joint,
+                                const double* __restrict__ marg_a,
+                                const double* __restrict__ marg_b,
+                                const double* __restrict__ nmap, long long S,
+                                int QA, int QB, double* __restrict__ mi,
+                                int32_t* __restrict__ n_out,
+                                uint32_t* __restrict__ maxn) {
+  const long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  uint32_t nn = 0u;
+  if (o < S) {
+    const double nr = fmax(rint(nmap[o]), 0.0);
+    nn = (uint32_t)nr;
+    double v = 0.0;
+    if (nn > 0u) {
+      double sab = 0.0, sa = 0.0, sb = 0.0;
+      for (int p = 0; p < QA * QB; ++p) sab += plain_xlog(joint[p * S + o]);
+      for (int a = 0; a < QA; ++a) sa += plain_xlog(marg_a[a * S + o]);
+      for (int b = 0; b < QB; ++b) sb += plain_xlog(marg_b[b * S + o]);
+      v = log2(nr) + (sab - sa - sb) / nr;
+    }
+    mi[o] = v;
+    n_out[o] = (int32_t)nn;
+  }
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    const uint32_t t = __shfl_xor(nn, s, 64);
+    nn = t > nn ? t : nn;
+  }
+  if ((threadIdx.x % 64) == 0) atomicMax(maxn, nn);
+}
+
+hipError_t launch_plain_entropy(const PlainEntropyArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain_entropy, dim3((unsigned)((a.S + 255) / 256)), dim3(256),
+                     0, st, a.joint, a.marg_a, a.marg_b, a.nmap, a.S, a.QA, a.QB,
+                     a.mi, a.n, a.maxn);
+  return hipGetLastError();
+}
+
 hipError_t launch_argmax(const ArgmaxArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_argmax_partial, dim3(a.nchunks, a.nb), dim3(256), 0, st,
                      a.mi, a.n, a.angle_stride, a.maxn, a.sh, a.sw,

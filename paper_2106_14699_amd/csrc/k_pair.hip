@@ -62,6 +62,20 @@ __device__ __forceinline__ void pair_cols_run(
     const TWS& ftw, C2<T>* smem, int c, int team, int lane) {
   constexpr int R = P / TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
+  if (fa_col == nullptr) {
+    // the B operand already holds the product spectra (plain schedule)
+    for (int b = b_begin; b < b_end; ++b) {
+      const C2<T>* fb_col = fb_base + b * fb_label_stride;
+      C2<T> v[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = fb_col[lane + TEAM * q];
+      team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
+      pair_cols_store<T, P, TEAM>(
+          v, smem, z_base + (long long)(zpair0 + b - b_begin) * z_pair_stride, ha,
+          hb, sh, team, lane);
+    }
+    return;
+  }
   C2<T> fa[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) fa[q] = fa_col[lane + TEAM * q];
@@ -149,7 +163,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
   const int c = t * TW + team;
-  const C2<T>* fa_col = FA + a * fa_label_stride + (long long)c * P;
+  const C2<T>* fa_col = FA ? FA + a * fa_label_stride + (long long)c * P : nullptr;
   const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
   if constexpr (pair_cols_lds_twiddles<T, P>()) {
     C2<T>* twl = smem + TW * lds_elems(P);

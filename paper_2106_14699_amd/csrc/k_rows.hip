@@ -19,6 +19,8 @@
 //     a fixed order, and MI = log2 N + (S_AB - S_A - S_B) / N is written.
 // k_pair_counts: the same row transforms, writing the rounded joint counts
 // and/or their order-free digests instead of entropies.
+#include <type_traits>
+
 #include "entropy.h"
 #include "fft_core.h"
 #include "internal.h"
@@ -27,7 +29,9 @@
 
 namespace cmif {
 
-template <typename T, int P, int TEAM, int BPW, int NTMAX>
+// RERUN selects the FP64 re-run variant (angle gates, count overrides): a
+// kernel of its own so that the main pass carries none of that code.
+template <typename T, int P, int TEAM, int BPW, int NTMAX, bool RERUN>
 __global__ void __launch_bounds__(NTMAX)
 k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
@@ -41,7 +45,9 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             const int32_t* __restrict__ ovc) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
-  if (gate != nullptr && gate[blockIdx.y] == 0u) return;
+  if constexpr (RERUN) {
+    if (gate[blockIdx.y] == 0u) return;
+  }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nteams = blockDim.x / TEAM;
   const int NT = blockDim.x;
@@ -122,7 +128,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
                                  nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
         }
         team_fft<T, P, TEAM, +1>(w, lds, ftw, lane);
-        if (ovr != nullptr) {
+        if constexpr (RERUN) {
           // re-run: pairs recomputed in FP64 enter with their exact counts
           // (count * P_h P_w is exact, so the rounding below returns it)
           const int o0 = has0 ? ovr[beta * nq + a * QB + b0] : -1;
@@ -177,7 +183,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         }
         if (!has1) e1max = 0.0f;
         maxres = fmaxf(maxres, fmaxf(e0max, e1max));
-        if (flags != nullptr) {
+        if (!RERUN && flags != nullptr) {
           if (__ballot(has0 && e0max >= 0.25f) != 0ull && (tid % 64) == 0) {
             const uint32_t old = atomicOr(&flags[beta * nq + a * QB + b0], 1u);
             if (old == 0u && stats) atomicAdd(&stats->flagged_pairs, 1u);
@@ -263,7 +269,8 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
               long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
               int sw, int ph, const C2<T>* __restrict__ tw,
               int32_t* __restrict__ counts, long long counts_angle_stride,
-              uint64_t* __restrict__ digest, const int4* __restrict__ items,
+              uint64_t* __restrict__ digest, double* __restrict__ values,
+              const int4* __restrict__ items,
               const uint32_t* __restrict__ n_items,
               int32_t* __restrict__ item_counts) {
   constexpr int R = P / TEAM;
@@ -323,6 +330,11 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
           item_counts[(long long)p0 * sh * sw + o] = (int32_t)n0;
           if (has1) item_counts[(long long)p1 * sh * sw + o] = (int32_t)n1;
         }
+        if (values) {
+          double* vb = values + beta * counts_angle_stride;
+          vb[(long long)p0 * sh * sw + o] = (double)(w[q].x * scale);
+          if (has1) vb[(long long)p1 * sh * sw + o] = (double)(w[q].y * scale);
+        }
         const uint64_t wgt = splitmix64((uint64_t)o);
         d0 += (uint64_t)n0 * wgt;
         d1 += (uint64_t)n1 * wgt;
@@ -342,11 +354,11 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
   }
 }
 
-template <typename T, int P, int BPW, int NTMAX>
+template <typename T, int P, int BPW, int NTMAX, bool RERUN>
 static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm,
                                 hipStream_t st) {
   constexpr int TEAM = team_for(P);
-  auto fn = k_pair_rows<T, P, TEAM, BPW, NTMAX>;
+  auto fn = k_pair_rows<T, P, TEAM, BPW, NTMAX, RERUN>;
   hipError_t e = hipFuncSetAttribute((const void*)fn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
@@ -361,12 +373,27 @@ static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm
   return hipGetLastError();
 }
 
+template <typename T, int P, int BPW, bool RERUN>
+static hipError_t launch_pr_rr(const PairRowsArgs<T>& a, const PairRowsConfig& c,
+                               hipStream_t st) {
+  if (c.ntmax <= 256) return launch_pr_cfg<T, P, BPW, 256, RERUN>(a, c.nteams, c.lds, st);
+  if (c.ntmax <= 512) return launch_pr_cfg<T, P, BPW, 512, RERUN>(a, c.nteams, c.lds, st);
+  return launch_pr_cfg<T, P, BPW, 1024, RERUN>(a, c.nteams, c.lds, st);
+}
+
 template <typename T, int P, int BPW>
 static hipError_t launch_pr_bpw(const PairRowsArgs<T>& a, const PairRowsConfig& c,
                                 hipStream_t st) {
-  if (c.ntmax <= 256) return launch_pr_cfg<T, P, BPW, 256>(a, c.nteams, c.lds, st);
-  if (c.ntmax <= 512) return launch_pr_cfg<T, P, BPW, 512>(a, c.nteams, c.lds, st);
-  return launch_pr_cfg<T, P, BPW, 1024>(a, c.nteams, c.lds, st);
+  // the FP64 re-run exists for the FP32 pass only
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.ovr != nullptr) {
+      if (a.gate == nullptr || a.ovc == nullptr) return hipErrorInvalidValue;
+      return launch_pr_rr<T, P, BPW, true>(a, c, st);
+    }
+  } else {
+    if (a.ovr != nullptr) return hipErrorInvalidValue;
+  }
+  return launch_pr_rr<T, P, BPW, false>(a, c, st);
 }
 
 // One (precision, FFT length) per object file: the build compiles this file
@@ -397,7 +424,7 @@ hipError_t launch_pair_counts_p(const PairCountsArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
                      a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
                      a.sh, a.sw, a.ph, a.tw, a.counts, a.counts_angle_stride,
-                     a.digest, a.items, a.n_items, a.item_counts);
+                     a.digest, a.values, a.items, a.n_items, a.item_counts);
   return hipGetLastError();
 }
 

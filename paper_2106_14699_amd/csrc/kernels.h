@@ -17,6 +17,7 @@ struct FwdRowsArgs {
   const float* memb;   // nullable: soft memberships [Q][H][W] replace lab
   cmif_stats* stats;   // nullable (soft: non-finite memberships)
   int H, W, Q, nb;
+  int label0;          // hard: labels label0 .. label0+Q-1 are transformed
   RotArgs rot;
   C2<T>* xrow;
   long long angle_stride;
@@ -40,7 +41,7 @@ struct FwdColsArgs {
 
 template <typename T>
 struct PairColsArgs {
-  const C2<T>* FA;
+  const C2<T>* FA;     // nullable: FB already holds the product spectra
   long long fa_label_stride;
   const C2<T>* FB;
   long long fb_angle_stride, fb_label_stride;
@@ -87,6 +88,7 @@ struct PairCountsArgs {
   int32_t* counts;       // nullable, [nb][QA*QB][sh][sw]
   long long counts_angle_stride;
   uint64_t* digest;      // nullable, [nb][QA*QB], accumulated (zero first)
+  double* values;        // nullable, [nb][QA*QB][sh][sw] unrounded values
   // item mode (nullable): Z holds one pair per item slot (no angle stride);
   // item s = (angle, a, b) writes to the (angle, a*QB+b) outputs above and,
   // when item_counts is given, to item_counts[s][sh][sw]
@@ -259,6 +261,24 @@ hipError_t launch_check_labels(const uint8_t* lab, const uint8_t* msk,
                                hipStream_t st);
 hipError_t launch_argmax(const ArgmaxArgs& a, hipStream_t st);
 hipError_t launch_fb_list(const FbListArgs& a, hipStream_t st);
+
+// Plain schedule: conjugate spectral product of one pair of 2D half
+// spectra, and the per-displacement entropy reduction over materialised
+// count maps.
+hipError_t launch_plain_product(const C2<double>* fa, const C2<double>* fb,
+                                C2<double>* y, int half, int ph, hipStream_t st);
+struct PlainEntropyArgs {
+  const double* joint;   // [QA*QB][S]
+  const double* marg_a;  // [QA][S]
+  const double* marg_b;  // [QB][S]
+  const double* nmap;    // [S]
+  long long S;
+  int QA, QB;
+  double* mi;            // [S]
+  int32_t* n;            // [S]
+  uint32_t* maxn;        // [1]
+};
+hipError_t launch_plain_entropy(const PlainEntropyArgs& a, hipStream_t st);
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
 
 }  // namespace cmif

@@ -235,6 +235,19 @@ def test_soft_plans(cm):
         cm.cmif_plan_free(h1)
 
 
+def test_plain_schedule_plans(cm):
+    plain = cm.CMIF_FLAG_PLAIN_SCHEDULE
+    d = make_desc(cm)
+    d.flags, d.precision = plain, cm.CMIF_PREC_FP64
+    assert plan_status(cm, d) == 0
+    d = make_desc(cm)
+    d.flags, d.precision = plain, cm.CMIF_PREC_FP32_ROUNDED
+    assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
+    d = make_desc(cm)
+    d.flags, d.precision, d.mode = plain, cm.CMIF_PREC_FP64, cm.CMIF_MODE_SOFT
+    assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
+
+
 def test_status_strings(cm):
     seen = set()
     for s in range(8):
