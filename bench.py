@@ -62,7 +62,7 @@ def hot_sources():
     c = os.path.join(ROOT, "paper_2106_14699_amd", "csrc")
     return [os.path.join(c, f) for f in ("k_rows.hip", "k_pair.hip",
                                          "fft_core.h", "entropy.h",
-                                         "internal.h")]
+                                         "internal.h", "rows_common.h")]
 
 
 def read_traffic(stage):
