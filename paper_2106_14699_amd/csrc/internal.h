@@ -53,6 +53,16 @@ constexpr int col_team_for(int p) {
                                                : 1024 / tile_width<T>();
 }
 
+// Team size of the pair column kernel: one wave per column up to P = 1024
+// (16 points per lane: radix 16, 16, 4 with two LDS exchanges and wave-level
+// barriers only), P/16 lanes above, capped so that TW teams fit 1024 lanes.
+template <typename T>
+constexpr int pair_col_team(int p) {
+  return (p <= 1024 ? 64 : p / 16) * tile_width<T>() <= 1024
+             ? (p <= 1024 ? 64 : p / 16)
+             : 1024 / tile_width<T>();
+}
+
 // Column swizzle of a [rows][TW] LDS staging tile: element (row, col) lives
 // at row*TW + (col ^ stage_swz(row)).  The swizzle is a multiple of
 // 16 B / sizeof(element) so 16-byte vectors of a row stay contiguous, and

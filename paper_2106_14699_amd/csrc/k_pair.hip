@@ -132,17 +132,29 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
             long long fb_label_stride, int QB, int ha, int hb, int sh,
             C2<T>* __restrict__ Z, long long z_angle_stride,
             long long z_pair_stride, const C2<T>* __restrict__ tw,
-            const int4* __restrict__ items, const uint32_t* __restrict__ n_items) {
+            const int4* __restrict__ items, const uint32_t* __restrict__ n_items,
+            int xcd_groups) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int TW = tile_width<T>();
-  const int t = blockIdx.x;
+  int t = blockIdx.x;
   int a, beta, b_begin, b_end, zpair0;
   C2<T>* z_base;
   if (items == nullptr) {
     // all pairs: workgroup (tile, a, angle) runs every b
     a = blockIdx.y;
     beta = blockIdx.z;
+    if (xcd_groups) {
+      // consecutive workgroup ids go to consecutive XCDs (8): give each XCD
+      // whole (angle, tile) groups, so that the Q_A workgroups that read
+      // one tile's F_B columns share that XCD's L2
+      const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      const int s = L >> 3;
+      const int grp = (L & 7) + 8 * (s / (int)gridDim.y);
+      a = s % (int)gridDim.y;
+      t = grp % (int)gridDim.x;
+      beta = grp / (int)gridDim.x;
+    }
     b_begin = 0;
     b_end = QB;
     zpair0 = a * QB;
@@ -184,7 +196,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
 
 template <typename T, int P>
 static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
-  constexpr int TEAM = col_team_for<T>(P);
+  constexpr int TEAM = pair_col_team<T>(P);
   constexpr int TW = tile_width<T>();
   const size_t shm = pair_cols_exch_bytes<T, P>() +
                      (pair_cols_lds_twiddles<T, P>() ? (size_t)P * sizeof(C2<T>) : 0);
@@ -194,10 +206,11 @@ static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
                                      (int)shm);
   if (e != hipSuccess) return e;
   dim3 grid = a.items ? dim3(a.tiles, a.max_items, 1) : dim3(a.tiles, a.QA, a.nb);
+  const int xcd_groups = !a.items && ((long long)a.tiles * a.nb) % 8 == 0;
   hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.FA, a.fa_label_stride,
                      a.FB, a.fb_angle_stride, a.fb_label_stride, a.QB, a.ha,
                      a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw,
-                     a.items, a.n_items);
+                     a.items, a.n_items, xcd_groups);
   return hipGetLastError();
 }
 
