@@ -23,8 +23,24 @@ constexpr size_t pair_cols_exch_bytes() {
   return (size_t)tile_width<T>() * lds_elems(P) * sizeof(C2<T>);
 }
 template <typename T, int P>
+constexpr size_t pair_cols_stage_bytes() {
+  return (size_t)P * tile_width<T>() * sizeof(C2<T>);
+}
+// A staging tile of its own (instead of the exchange buffers) when it fits:
+// one barrier less per label b, and the copy-out of b overlaps the next FFT.
+template <typename T, int P>
+constexpr bool pair_cols_sep_staging() {
+  return pair_cols_exch_bytes<T, P>() + pair_cols_stage_bytes<T, P>() +
+             (size_t)P * sizeof(C2<T>) <= 160 * 1024;
+}
+template <typename T, int P>
+constexpr size_t pair_cols_table_offset() {
+  return pair_cols_exch_bytes<T, P>() +
+         (pair_cols_sep_staging<T, P>() ? pair_cols_stage_bytes<T, P>() : 0);
+}
+template <typename T, int P>
 constexpr bool pair_cols_lds_twiddles() {
-  return pair_cols_exch_bytes<T, P>() + (size_t)P * sizeof(C2<T>) <= 160 * 1024;
+  return pair_cols_table_offset<T, P>() + (size_t)P * sizeof(C2<T>) <= 160 * 1024;
 }
 
 // Staging + store of one b's TW columns: rows i of the tile leave as 16-byte
@@ -37,19 +53,25 @@ __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* sme
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   constexpr int EV = 16 / (int)sizeof(C2<T>);
-  __syncthreads();  // every team is done with its exchange buffer
+  constexpr bool SEP = pair_cols_sep_staging<T, P>();
+  C2<T>* stage = SEP ? reinterpret_cast<C2<T>*>(reinterpret_cast<unsigned char*>(smem) +
+                                                 pair_cols_exch_bytes<T, P>())
+                     : smem;
+  // separate tile: the previous copy-out has finished reading it; aliased
+  // tile: every team is done with its exchange buffer
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = circ_to_map(lane + TEAM * q, P, ha, hb);
-    if (i >= 0) smem[i * TW + (team ^ stage_swz<TW>(i))] = v[q];
+    if (i >= 0) stage[i * TW + (team ^ stage_swz<TW>(i))] = v[q];
   }
   __syncthreads();
   float4* z4 = reinterpret_cast<float4*>(zp);
   for (int e = threadIdx.x; e < sh * TW / EV; e += blockDim.x) {
     const int i = (e * EV) / TW, col = (e * EV) % TW;
-    z4[e] = *reinterpret_cast<const float4*>(&smem[i * TW + (col ^ stage_swz<TW>(i))]);
+    z4[e] = *reinterpret_cast<const float4*>(&stage[i * TW + (col ^ stage_swz<TW>(i))]);
   }
-  __syncthreads();
+  if constexpr (!SEP) __syncthreads();  // the exchange buffers are reused next
 }
 
 // Runs labels b in [b_begin, b_end) of B against label a of A; output pair
@@ -178,7 +200,8 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
   const C2<T>* fa_col = FA ? FA + a * fa_label_stride + (long long)c * P : nullptr;
   const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
   if constexpr (pair_cols_lds_twiddles<T, P>()) {
-    C2<T>* twl = smem + TW * lds_elems(P);
+    C2<T>* twl = reinterpret_cast<C2<T>*>(reinterpret_cast<unsigned char*>(smem) +
+                                          pair_cols_table_offset<T, P>());
     for (int x = threadIdx.x; x < P; x += blockDim.x) twl[x] = tw[x];
     __syncthreads();
     const FftTwTable<T, P, TEAM> ftw{twl};
@@ -198,7 +221,7 @@ template <typename T, int P>
 static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = pair_col_team<T>(P);
   constexpr int TW = tile_width<T>();
-  const size_t shm = pair_cols_exch_bytes<T, P>() +
+  const size_t shm = pair_cols_table_offset<T, P>() +
                      (pair_cols_lds_twiddles<T, P>() ? (size_t)P * sizeof(C2<T>) : 0);
   auto fn = k_pair_cols<T, P, TEAM>;
   hipError_t e = hipFuncSetAttribute((const void*)fn,
