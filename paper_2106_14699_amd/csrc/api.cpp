@@ -145,7 +145,8 @@ size_t elem_bytes(const cmif_plan_s& P) {
   return P.d.precision == CMIF_PREC_FP64 ? sizeof(double2) : sizeof(float2);
 }
 
-int rows_per_chunk(int sh) { return (sh + 63) / 64; }
+// argmax chunks: about 256 per angle (a few map rows each)
+int rows_per_chunk(int sh) { return (sh + 255) / 256; }
 
 ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
   const size_t E = elem_bytes(P);

@@ -234,7 +234,7 @@ hipError_t launch_fwd_rows(int P, const FwdRowsArgs<T>& a, hipStream_t st) {
 
 template <typename T, int P>
 static hipError_t launch_cols_p(const FwdColsArgs<T>& a, hipStream_t st) {
-  constexpr int TEAM = col_team_for<T>(P);
+  constexpr int TEAM = pair_col_team<T>(P);
   constexpr int TW = tile_width<T>();
   const size_t shm = (size_t)TW * lds_elems(P) * sizeof(C2<T>);
   auto fn = k_fwd_cols<T, P, TEAM>;

@@ -304,14 +304,53 @@ struct AngleVals {
   double v[kMaxBatch];
 };
 
-__global__ void k_argmax_final(const ArgPartial* __restrict__ partial, int nb,
-                               int nchunks, int sw, int ha, int wa, int angle0,
-                               AngleVals angles,
-                               cmif_best* __restrict__ per_angle,
-                               cmif_best* __restrict__ running, int first_batch,
-                               cmif_best* __restrict__ best_out,
-                               int last_batch) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(64 * kMaxBatch)
+k_argmax_final(const ArgPartial* __restrict__ partial, int nb, int nchunks,
+               int sw, int ha, int wa, int angle0, AngleVals angles,
+               cmif_best* __restrict__ per_angle, cmif_best* __restrict__ running,
+               int first_batch, cmif_best* __restrict__ best_out,
+               int last_batch) {
+  __shared__ cmif_best res[kMaxBatch];
+  // wave b reduces angle b's chunk partials (the order of a max with the
+  // smaller-index tie rule does not matter)
+  const int b = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (b < nb) {
+    double bm = 0.0;
+    long long bi = -1;
+    long long bn = 0;
+    for (int c = l; c < nchunks; c += 64) {
+      const ArgPartial p = partial[b * nchunks + c];
+      if (better(p.mi, p.idx, bm, bi)) { bm = p.mi; bi = p.idx; bn = p.n; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double om = __shfl_xor(bm, o, 64);
+      const long long oi = __shfl_xor(bi, o, 64);
+      const long long on = __shfl_xor(bn, o, 64);
+      if (better(om, oi, bm, bi)) { bm = om; bi = oi; bn = on; }
+    }
+    if (l == 0) {
+      cmif_best r;
+      r.angle_index = angle0 + b;
+      r.angle_rad = angles.v[b];
+      r.reserved = 0;
+      if (bi >= 0) {
+        r.dy = (int)(bi / sw) - (ha - 1);
+        r.dx = (int)(bi % sw) - (wa - 1);
+        r.mi = bm;
+        r.n = bn;
+      } else {
+        r.dy = 0;
+        r.dx = 0;
+        r.mi = 0.0;
+        r.n = 0;
+      }
+      res[b] = r;
+      if (per_angle) per_angle[angle0 + b] = r;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   cmif_best run = *running;
   if (first_batch) {
     run.angle_index = -1;
@@ -322,32 +361,10 @@ __global__ void k_argmax_final(const ArgPartial* __restrict__ partial, int nb,
     run.mi = 0.0;
     run.n = 0;
   }
-  for (int b = 0; b < nb; ++b) {
-    double bm = 0.0;
-    long long bi = -1;
-    long long bn = 0;
-    for (int c = 0; c < nchunks; ++c) {
-      const ArgPartial p = partial[b * nchunks + c];
-      if (better(p.mi, p.idx, bm, bi)) { bm = p.mi; bi = p.idx; bn = p.n; }
-    }
-    cmif_best r;
-    r.angle_index = angle0 + b;
-    r.angle_rad = angles.v[b];
-    r.reserved = 0;
-    if (bi >= 0) {
-      r.dy = (int)(bi / sw) - (ha - 1);
-      r.dx = (int)(bi % sw) - (wa - 1);
-      r.mi = bm;
-      r.n = bn;
-    } else {
-      r.dy = 0;
-      r.dx = 0;
-      r.mi = 0.0;
-      r.n = 0;
-    }
-    if (per_angle) per_angle[angle0 + b] = r;
-    if (r.mi > run.mi) run = r;  // I starts at 0 with the identity
-  }
+  // angles in order: I starts at 0 with the identity, a strictly larger MI
+  // replaces the best (the earliest angle wins ties)
+  for (int k = 0; k < nb; ++k)
+    if (res[k].mi > run.mi) run = res[k];
   *running = run;
   if (last_batch && best_out) *best_out = run;
 }
@@ -355,7 +372,8 @@ __global__ void k_argmax_final(const ArgPartial* __restrict__ partial, int nb,
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st) {
   AngleVals av;
   for (int b = 0; b < kMaxBatch; ++b) av.v[b] = a.angles[b];
-  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, st, a.partial, a.nb,
+  if (a.nb < 1 || a.nb > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64 * a.nb), 0, st, a.partial, a.nb,
                      a.nchunks, a.sw, a.ha, a.wa, a.angle0, av,
                      a.per_angle, a.running, a.first_batch, a.best_out,
                      a.last_batch);
