@@ -199,7 +199,9 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
 // ---------------------------------------------------------------------------
 template <typename T, int P>
 static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
-  constexpr int TEAM = team_for(P);
+  // FP32: one-wave teams up to P = 1024; FP64 keeps P/8 lanes above 512
+  // (16 double points per lane do not fit the registers)
+  constexpr int TEAM = sizeof(T) == 4 ? pair_col_team<T>(P) : team_for(P);
   const int npacks = (a.Q + 1) / 2;
   const size_t per_team = (size_t)lds_elems(P) * sizeof(C2<T>);
   int nteams = npacks;
