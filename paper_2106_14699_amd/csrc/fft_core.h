@@ -166,7 +166,7 @@ struct FftTw {
   C2<T> w[fft_tw_count<N, TEAM>() > 0 ? fft_tw_count<N, TEAM>() : 1];
 };
 
-template <typename T, int N, int TEAM, int NS, int OFF>
+template <typename T, int N, int TEAM, int NS, int OFF, int MUL>
 __device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM>& f,
                                              const C2<T>* __restrict__ tw,
                                              int lane) {
@@ -181,20 +181,21 @@ __device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM>& f,
       const int k = (lane + TEAM * t) & (NS - 1);
 #pragma unroll
       for (int m = 1; m < RAD; ++m)
-        f.w[OFF + t * (RAD - 1) + (m - 1)] = tw[m * k * TSTRIDE];
+        f.w[OFF + t * (RAD - 1) + (m - 1)] = tw[m * k * TSTRIDE * MUL];
     }
   }
   if constexpr (!LAST)
     fft_tw_stage<T, N, TEAM, NS * RAD,
-                 OFF + (NS > 1 ? BPL * (RAD - 1) : 0)>(f, tw, lane);
+                 OFF + (NS > 1 ? BPL * (RAD - 1) : 0), MUL>(f, tw, lane);
 }
 
-// Fills a lane's twiddles from the table tw[t] = exp(+2 pi i t / N).
-template <typename T, int N, int TEAM>
+// Fills a lane's twiddles from the table tw[t] = exp(+2 pi i t / (N MUL))
+// (MUL > 1: the table of a longer transform, every MUL-th entry used).
+template <typename T, int N, int TEAM, int MUL = 1>
 __device__ __forceinline__ void fft_load_twiddles(FftTw<T, N, TEAM>& f,
                                                   const C2<T>* __restrict__ tw,
                                                   int lane) {
-  fft_tw_stage<T, N, TEAM, 1, 0>(f, tw, lane);
+  fft_tw_stage<T, N, TEAM, 1, 0, MUL>(f, tw, lane);
 }
 
 // Twiddle source reading the N-entry table exp(+2 pi i t/N) from LDS (or any
@@ -271,6 +272,41 @@ __device__ __forceinline__ void team_fft(C2<T> (&v)[N / TEAM], C2<T>* lds,
   static_assert(N % TEAM == 0 && N / TEAM >= 2, "team too large for N");
   static_assert((N & (N - 1)) == 0, "power-of-two lengths only");
   fft_stage<T, N, TEAM, DIR, 1, 0, TWS>(v, lds, f, lane);
+}
+
+// Length-P transform over two waves (TEAM = 128, R = P/128 points per
+// lane) with a single workgroup barrier: the decimation-in-time split of
+// the sequence into even and odd samples.  Wave w (0 or 1) holds x[2n + w]
+// at n = l + 64 q (l = lane in the wave, q < R), transforms them at length
+// P/2 alone (one-wave Stockham: wave-level barriers only), and one exchange
+// through `cross` (2 x P/2 elements, distinct from the buffer of the previous
+// call) joins the halves:
+//   X[m] = E[m] + W^m O[m],  X[m + P/2] = E[m] - W^m O[m],  W = exp(DIR 2 pi i / P).
+// On return wave w holds X[w P/2 + l + 64 q].  wm[q] = exp(+2 pi i m / P) at
+// m = l + 64 q; f_half: twiddles of the length-P/2 transform.  Every lane of
+// the workgroup must call it (it contains __syncthreads).
+template <typename T, int P, int DIR, class TWS>
+__device__ __forceinline__ void team2_fft(C2<T> (&v)[P / 128], C2<T>* lds_w,
+                                          C2<T>* cross, const TWS& f_half,
+                                          const C2<T> (&wm)[P / 128], int wave,
+                                          int l) {
+  constexpr int R = P / 128;
+  team_fft<T, P / 2, 64, DIR>(v, lds_w, f_half, l);
+  C2<T>* mine = cross + wave * (P / 2);
+  const C2<T>* other = cross + (1 - wave) * (P / 2);
+#pragma unroll
+  for (int q = 0; q < R; ++q) mine[l + 64 * q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const C2<T> o = other[l + 64 * q];
+    const C2<T> e = wave == 0 ? v[q] : o;
+    const C2<T> od = wave == 0 ? o : v[q];
+    C2<T> w = wm[q];
+    if constexpr (DIR < 0) w.y = -w.y;
+    const C2<T> t = cmul<T>(w, od);
+    v[q] = wave == 0 ? cadd<T>(e, t) : csub<T>(e, t);
+  }
 }
 
 }  // namespace cmif

@@ -66,8 +66,31 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 
   for (int x = tid; x < 512; x += NT) ltab[x] = logtab_g[x];
   for (int x = tid; x < kXlogN; x += NT) xlt[x] = xlogtab_g[x];
-  FftTw<T, P, TEAM> ftw;
-  fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
+  // SPLIT (FP32, two-wave teams): each row transform is two one-wave
+  // half-length transforms joined by one exchange, so it takes one
+  // workgroup barrier instead of one per Stockham exchange
+  constexpr bool SPLIT = TEAM == 128 && sizeof(T) == 4;
+  FftTw<T, SPLIT ? P / 2 : P, SPLIT ? 64 : TEAM> ftw;
+  C2<T> wm[SPLIT ? R : 1];
+  if constexpr (SPLIT) {
+    fft_load_twiddles<T, P / 2, 64, 2>(ftw, tw, lane & 63);
+#pragma unroll
+    for (int q = 0; q < R; ++q) wm[q] = tw[(lane & 63) + 64 * q];
+  } else {
+    fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
+  }
+  C2<T>* lds_w = lds + (lane >> 6) * lds_elems(P / 2);  // SPLIT: per wave
+  C2<T>* cross = reinterpret_cast<C2<T>*>(slot + 2 * P) + team * 2 * P;
+  int nfft = 0;  // alternates the exchange buffers of consecutive transforms
+  auto row_fft = [&](C2<T> (&v)[R]) {
+    if constexpr (SPLIT) {
+      team2_fft<T, P, +1>(v, lds_w, cross + (nfft & 1) * P, ftw, wm, lane >> 6,
+                          lane & 63);
+      ++nfft;
+    } else {
+      team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
+    }
+  };
 
   const T scale = (T)1 / ((T)ph * (T)P);
   const int tile_stride = sh * TW;
@@ -98,9 +121,9 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     {
       const int b0 = b_first, b1 = b0 + 1;
       if (b0 < QB)
-        load_raw<T, P, TEAM>(zrow + (long long)b0 * z_pair_stride,
-                             zrow + (long long)b1 * z_pair_stride, b1 < QB,
-                             tile_stride, lane, nu0, nu1);
+        load_raw<T, P, TEAM, SPLIT>(zrow + (long long)b0 * z_pair_stride,
+                                    zrow + (long long)b1 * z_pair_stride, b1 < QB,
+                                    tile_stride, lane, nu0, nu1);
     }
     for (int a = 0; a < QA; ++a) {
       uint32_t* sl = slot + (a & 1) * P;
@@ -113,7 +136,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         const bool has0 = b0 < QB, has1 = b1 < QB;
         C2<T> w[R];
         if (has0) {
-          build_pack<T, P, TEAM>(nu0, nu1, lane, w);
+          build_pack<T, P, TEAM, SPLIT>(nu0, nu1, lane, w);
         } else {
 #pragma unroll
           for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
@@ -123,11 +146,12 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
           const int na = pk + 1 < BPW / 2 ? a : a + 1;
           const int nb0 = pk + 1 < BPW / 2 ? b0 + 2 : b_first;
           if (na < QA && nb0 < QB)
-            load_raw<T, P, TEAM>(zrow + (long long)(na * QB + nb0) * z_pair_stride,
-                                 zrow + (long long)(na * QB + nb0 + 1) * z_pair_stride,
-                                 nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
+            load_raw<T, P, TEAM, SPLIT>(
+                zrow + (long long)(na * QB + nb0) * z_pair_stride,
+                zrow + (long long)(na * QB + nb0 + 1) * z_pair_stride,
+                nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
         }
-        team_fft<T, P, TEAM, +1>(w, lds, ftw, lane);
+        row_fft(w);
         if constexpr (RERUN) {
           // re-run: pairs recomputed in FP64 enter with their exact counts
           // (count * P_h P_w is exact, so the rounding below returns it)
@@ -139,7 +163,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             const long long mstride = (long long)sh * sw;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-              const int j = circ_to_map(lane + TEAM * q, P, wa, wb);
+              const int j = circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb);
               if (j >= 0) {
                 if (o0 >= 0) w[q].x = (T)ovc[o0 * mstride + mrow + j] * unscale;
                 if (o1 >= 0) w[q].y = (T)ovc[o1 * mstride + mrow + j] * unscale;
@@ -152,7 +176,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         uint32_t big = 0u;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          if (circ_to_map(lane + TEAM * q, P, wa, wb) >= 0) {
+          if (circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
             const T v0 = w[q].x * scale, v1 = w[q].y * scale;
             const T r0 = round_half_even<T>(v0), r1 = round_half_even<T>(v1);
             e0max = fmaxf(e0max, (float)fabs(v0 - r0));
@@ -171,7 +195,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
           // rare: counts beyond the table, replace the clamped entries
 #pragma unroll
           for (int q = 0; q < R; ++q) {
-            if (circ_to_map(lane + TEAM * q, P, wa, wb) >= 0) {
+            if (circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
               const uint32_t n0 = (uint32_t)fmax(round_half_even<T>(w[q].x * scale), (T)0);
               const uint32_t n1 = (uint32_t)fmax(round_half_even<T>(w[q].y * scale), (T)0);
               if (n0 >= (uint32_t)kXlogN)
@@ -197,7 +221,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
       // exact C_a = sum over all teams' b of C_ab (integer atomics)
 #pragma unroll
       for (int q = 0; q < R; ++q)
-        if (ca[q] != 0u) atomicAdd(&sl[lane + TEAM * q], ca[q]);
+        if (ca[q] != 0u) atomicAdd(&sl[row_out_pos<P, TEAM, SPLIT>(lane, q)], ca[q]);
       __syncthreads();
       // C_a of this a is complete: fold it into S_A and N
       for (int x = tid; x < P; x += NT) {
@@ -224,7 +248,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     __syncthreads();
     double* part = reinterpret_cast<double*>(lds);
 #pragma unroll
-    for (int q = 0; q < R; ++q) part[lane + TEAM * q] = sab[q];
+    for (int q = 0; q < R; ++q) part[row_out_pos<P, TEAM, SPLIT>(lane, q)] = sab[q];
     __syncthreads();
 
     for (int x = tid; x < P; x += NT) {

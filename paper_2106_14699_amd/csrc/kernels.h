@@ -185,10 +185,15 @@ struct PairRowsConfig {
   size_t lds;
 };
 
+// LDS of the row kernel: exchange buffers, log tables, S_A and N per x, the
+// C_a slots and (FP32 two-wave teams) the split transform's two exchange
+// buffers per team.
 inline size_t pair_rows_lds(size_t elem_real, int P, int nteams) {
+  const bool split = elem_real == sizeof(float) && team_for(P) == 128;
   return (size_t)nteams * lds_elems(P) * 2 * elem_real +
          (512 + kXlogN) * sizeof(double) + (size_t)P * sizeof(double) +
-         3 * (size_t)P * sizeof(uint32_t);
+         3 * (size_t)P * sizeof(uint32_t) +
+         (split ? (size_t)nteams * 2 * P * 2 * elem_real : 0);
 }
 
 // false when no supported shape fits (LDS above 160 KiB or > 1024 lanes)

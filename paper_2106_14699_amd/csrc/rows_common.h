@@ -29,10 +29,26 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
+// Sequence index held by (lane, q) on input to a row transform: lane +
+// TEAM q, or (SPLIT: two-wave decimation-in-time transform, TEAM = 128) the
+// even samples in wave 0 and the odd ones in wave 1.
+template <int TEAM, bool SPLIT>
+__device__ __forceinline__ int row_in_pos(int lane, int q) {
+  if constexpr (SPLIT) return 2 * ((lane & 63) + 64 * q) + (lane >> 6);
+  else return lane + TEAM * q;
+}
+
+// Output index held by (lane, q) after the row transform.
+template <int P, int TEAM, bool SPLIT>
+__device__ __forceinline__ int row_out_pos(int lane, int q) {
+  if constexpr (SPLIT) return (lane >> 6) * (P / 2) + (lane & 63) + 64 * q;
+  else return lane + TEAM * q;
+}
+
 // Raw loads of row i of pairs p0 (and p1 when has1): element k of the half
-// spectrum that lane position k = lane + TEAM*q needs (its mirror P - k in
-// the upper half; slot 0 for k = 0 and k = P/2).
-template <typename T, int P, int TEAM>
+// spectrum that sequence index k (row_in_pos) needs (its mirror P - k in the
+// upper half; slot 0 for k = 0 and k = P/2).
+template <typename T, int P, int TEAM, bool SPLIT = false>
 __device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
                                          const C2<T>* __restrict__ z1,
                                          bool has1, int tile_stride, int lane,
@@ -43,7 +59,7 @@ __device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
   constexpr int HALF = P / 2;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int k = lane + TEAM * q;
+    const int k = row_in_pos<TEAM, SPLIT>(lane, q);
     const int kk = k > HALF ? P - k : k;
     const int e = kk == HALF ? 0 : kk;
     const int off = (e / TW) * tile_stride + (e % TW);
@@ -54,7 +70,7 @@ __device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
 
 // Packed complex sequence W(k) = Z_p0(k) + i Z_p1(k) from the raw loads
 // (Hermitian extension of both half spectra).
-template <typename T, int P, int TEAM>
+template <typename T, int P, int TEAM, bool SPLIT = false>
 __device__ __forceinline__ void build_pack(const C2<T> (&u0)[P / TEAM],
                                            const C2<T> (&u1)[P / TEAM], int lane,
                                            C2<T> (&w)[P / TEAM]) {
@@ -62,7 +78,7 @@ __device__ __forceinline__ void build_pack(const C2<T> (&u0)[P / TEAM],
   constexpr int HALF = P / 2;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int k = lane + TEAM * q;
+    const int k = row_in_pos<TEAM, SPLIT>(lane, q);
     const int kk = k > HALF ? P - k : k;
     if (kk == 0)
       w[q] = mk<T>(u0[q].x, u1[q].x);
