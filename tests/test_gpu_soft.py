@@ -201,3 +201,49 @@ def test_soft_batch_uneven_pairs(gpu, oracle):
         i, j = b["dy"] + ha - 1, b["dx"] + wa - 1
         assert e[i, j]
         assert abs(omi[i, j] - omi[e].max()) <= 2e-5
+
+
+def test_soft_adjoint_vs_central_differences(gpu):
+    """The library's FP64 adjoint against central differences of its own
+    FP64 forward, on a tiny case (12x10 against 9x11, Q 3): L = sum_chi
+    w(chi) MI(chi) with fixed weights on eligible displacements."""
+    cm, torch = gpu
+    c = synth.random_soft_case(31, 12, 10, 9, 11, 3, mask_density=0.9)
+    sp = soft_plan(cm, (12, 10), (9, 11), 3, 3, "fp64")
+    MA, MB = dev(torch, c["MA"]), dev(torch, c["MB"])
+    n = sp.compute(fdev(torch, c["PA"]), MA, fdev(torch, c["PB"]), MB, mi=False,
+                   n=True)["n"][0][0].cpu().numpy()
+    w = np.random.default_rng(7).standard_normal(n.shape) * eligible(n)
+
+    def loss(pa, pb):
+        mi = sp.compute(fdev(torch, pa), MA, fdev(torch, pb), MB, mi=True,
+                        n=False)["mi"][0][0].cpu().numpy()
+        return float((mi * w).sum())
+
+    sp.compute(fdev(torch, c["PA"]), MA, fdev(torch, c["PB"]), MB, mi=True, n=False)
+    ga, gb = sp.backward(fdev(torch, c["PA"]), MA, fdev(torch, c["PB"]), MB,
+                         [torch.from_numpy(w[None]).cuda()])
+    ga, gb = ga[0].cpu().numpy(), gb[0].cpu().numpy()
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for side, base, g in (("A", c["PA"], ga), ("B", c["PB"], gb)):
+        mask = c["MA"] if side == "A" else c["MB"]
+        for _ in range(6):
+            q = int(rng.integers(0, base.shape[0]))
+            y = int(rng.integers(0, base.shape[1]))
+            x = int(rng.integers(0, base.shape[2]))
+            if not mask[y, x]:
+                continue
+            hp = base.copy()
+            hm = base.copy()
+            hp[q, y, x] = np.float32(base[q, y, x] + np.float32(2.0 ** -10))
+            hm[q, y, x] = np.float32(base[q, y, x] - np.float32(2.0 ** -10))
+            step = float(hp[q, y, x]) - float(hm[q, y, x])
+            if side == "A":
+                fd = (loss(hp, c["PB"]) - loss(hm, c["PB"])) / step
+            else:
+                fd = (loss(c["PA"], hp) - loss(c["PA"], hm)) / step
+            err = abs(fd - g[q, y, x]) / max(abs(fd), 1e-3)
+            worst = max(worst, err)
+            assert err <= 1e-3, (side, q, y, x, fd, g[q, y, x])
+    say(f"adjoint vs central differences: worst relative error {worst:.2e}")
