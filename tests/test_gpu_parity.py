@@ -183,3 +183,31 @@ def test_two_pairs_one_plan(gpu, oracle):
             o = oracle.cmif_direct(c["A"], c["MA"], bw, mw, 3, 4, counts=True)
             assert np.array_equal(res["counts"][p][k].cpu().numpy(), o["counts"])
             assert np.abs(res["mi"][p][k].cpu().numpy() - o["mi"]).max() <= MI_TOL
+
+
+def test_empty_overlap_everywhere(gpu, oracle):
+    """All of A masked out: N = 0 at every displacement, MI = 0 (Eq. 12
+    conventions), and Alg. 1 keeps the identity."""
+    cm, torch = gpu
+    c = synth.random_case(90, 33, 47, 29, 38, 4, 3, mask_density=0.7)
+    c = dict(c, MA=np.zeros_like(c["MA"]))
+    g = run_compute(gpu, c, "fp32", angles=[0.0, 0.7], digest=True,
+                    tag="all-masked")
+    assert not g["n"].any() and not g["mi"].any() and not g["counts"].any()
+    assert not g["digest"].any()
+    b = g["best"]
+    assert (b["angle_index"], b["dy"], b["dx"], b["mi"], b["n"]) == (-1, 0, 0, 0.0, 0)
+    o = oracle.cmif_direct(c["A"], c["MA"], c["B"], c["MB"], 4, 3)
+    assert not o["n"].any()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_max_labels_64(gpu, oracle, prec):
+    """Q_A = Q_B = 64 (the largest label count): 4096 label pairs."""
+    c = synth.random_case(64, 40, 36, 44, 30, 64, 64, mask_density=0.9,
+                          smooth=None)
+    g = run_compute(gpu, c, prec, digest=True, tag="q64")
+    o = oracle.cmif_direct(c["A"], c["MA"], c["B"], c["MB"], 64, 64,
+                           counts=True, digest=True)
+    check_map(oracle, g, o)
+    assert np.array_equal(g["digest"][0], o["digest"])
