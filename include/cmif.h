@@ -177,7 +177,10 @@ typedef struct cmif_inputs {
    image pair; each output is written for every angle of the plan. */
 typedef struct cmif_outputs {
   double* const* mi;       /* [n_angles][S_h][S_w] MI map in bits */
-  int32_t* const* n;       /* HARD: [n_angles][S_h][S_w] valid-point count */
+  int32_t* const* n;       /* [n_angles][S_h][S_w] valid-point count N
+                              (HARD: sum of the joint counts; SOFT: the
+                              mask overlap M_A corr M_B, exact, which is
+                              also the gamma threshold's N) */
   int32_t* const* counts;  /* HARD: [n_angles][q_a][q_b][S_h][S_w] joint */
   uint64_t* const* digest; /* HARD: [n_angles][q_a][q_b] order-free
                               fingerprint of each joint count map:
@@ -223,7 +226,11 @@ cmif_status cmif_workspace_size(cmif_plan_t plan, size_t* persistent,
    CMIF maps (Eq. 5, Sec. 3.2) for every image pair and angle, plus the
    Alg. 1 results when out->best / out->per_angle are given.  Any output may
    be NULL.  HARD plans read labels/masks, SOFT plans memberships/masks (and
-   ignore n, counts and digest). */
+   ignore counts and digest).  SOFT maps are real-valued joints (no
+   rounding, marginals and N of the MI from the joint sums, FP64 entropy
+   sums); with CMIF_FLAG_SAVE_FOR_BACKWARD the call keeps N, log2 N - MI and
+   the log2 marginals per displacement in the persistent workspace for
+   cmif_backward (valid until the next cmif_compute of the plan). */
 cmif_status cmif_compute(cmif_plan_t plan, const cmif_inputs* in,
                          const cmif_outputs* out, void* persistent,
                          size_t persistent_bytes, void* scratch,
@@ -238,11 +245,18 @@ cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
                        size_t persistent_bytes, void* scratch,
                        size_t scratch_bytes, void* stream);
 
-/* SOFT plans with CMIF_FLAG_SAVE_FOR_BACKWARD, after cmif_compute on the
-   same inputs: given dL/dMI (grad_mi[p], device [n_angles][S_h][S_w]
-   double), writes dL/dmemb_a (grad_a[p], [q_a][h_a][w_a] float) and
-   dL/dmemb_b (grad_b[p], [q_b][h_b][w_b] float), overwriting them.  Either
-   output array may be NULL to skip it. */
+/* SOFT plans with CMIF_FLAG_SAVE_FOR_BACKWARD (which cmif_plan accepts for
+   the single angle 0 only), after cmif_compute on the same inputs: given
+   dL/dMI (grad_mi[p], device [n_angles][S_h][S_w] double), writes
+   dL/dmemb_a (grad_a[p], [q_a][h_a][w_a] float) and dL/dmemb_b (grad_b[p],
+   [q_b][h_b][w_b] float), overwriting them; masked-out pixels get 0.
+   Either output array may be NULL to skip it.  Derivative: with G_ab(chi) =
+   dL/dMI(chi) (log2(C_ab N / (C_a C_b)) - MI(chi)) / N(chi) (0 where C_ab
+   or N is not positive), dL/dp_a(x) = sum_b sum_chi G_ab(chi) q_b(x + chi)
+   and dL/dq_b(y) = sum_a sum_chi G_ab(chi) p_a(y - chi), evaluated by FFTs
+   on the same grid as the forward.  Errors: CMIF_ERR_WRONG_MODE (HARD plan
+   or no SAVE_FOR_BACKWARD), CMIF_ERR_INVALID_ARGUMENT (NULL memberships or
+   grad_mi), workspace errors as cmif_compute. */
 cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
                           const double* const* grad_mi, float* const* grad_a,
                           float* const* grad_b, void* persistent,
