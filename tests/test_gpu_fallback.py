@@ -144,3 +144,11 @@ def test_precision_stress_1024_q2_full_overlap(gpu, oracle):
     # pair whose residual reaches 0.25 goes through the FP64 re-run
     c = synth.random_case(2106, 1024, 1024, 1024, 1024, 2, 2, mask_density=None)
     _stress(gpu, oracle, c, "1024x1024-q2")
+
+
+def test_precision_stress_1024_q1_full_overlap(gpu, oracle):
+    # one label over full masks: the joint count is N itself, up to 2^20 at
+    # zero displacement, the largest value any supported size produces
+    c = synth.random_case(2107, 1024, 1024, 1024, 1024, 1, 1, mask_density=None)
+    g = _stress(gpu, oracle, c, "1024x1024-q1")
+    assert int(g["n"][0].max()) == 1 << 20
