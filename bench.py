@@ -153,6 +153,10 @@ def main():
                     help="skip the soft-membership batch")
     ap.add_argument("--soft-steps", type=int, default=5)
     ap.add_argument("--copy-gib", type=float, default=0.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing "
+                         "the candidates in the warm-up call "
+                         "(CMIF_FLAG_AUTOTUNE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not "
@@ -173,7 +177,8 @@ def main():
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     A, MA, B, MB = dev(c["A"]), dev(c["MA"]), dev(c["B"]), dev(c["MB"])
     plan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
-                   gamma=c["gamma"], precision="fp32")
+                   gamma=c["gamma"], precision="fp32",
+                   flags=0 if args.no_autotune else cm.CMIF_FLAG_AUTOTUNE)
     n_maps = len(c["angles"])
 
     # warm-up: the first call captures the launch graph the timed steps replay
@@ -312,6 +317,9 @@ def main():
                                         float(np.median(step_ms)), 3)
                                   if plain else None),
         "soft": soft,
+        "launch_shapes": {k: info1[k] for k in ("rows_per_wg", "labels_per_team",
+                                                "xcd_grouping", "tuned",
+                                                "tune_runs")},
         "graph": dict(replays=replays, captures=info1["graph_captures"],
                       stage_steps=stage_steps,
                       eager_kernel_ms_per_step=round(eager_ms, 3)),

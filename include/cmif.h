@@ -109,7 +109,18 @@ enum {
      entropy kernel over all maps, and a host synchronisation before the next
      angle.  Same results; emits mi, n, best and per_angle (counts and
      digests are rejected) */
-  CMIF_FLAG_PLAIN_SCHEDULE = 1u << 3
+  CMIF_FLAG_PLAIN_SCHEDULE = 1u << 3,
+  /* HARD, fused schedule: the first cmif_compute / cmif_align call times
+     the candidate launch shapes of the pair row kernel (map rows per
+     workgroup 1, 2, 4 x labels of B per team 4, 8, 16 where they fit) and
+     the pair column kernel (XCD-grouped workgroup order on / off): one
+     untimed eager pass, then one eager pass per candidate on the call's own
+     buffers; keeps the fastest per kernel, then runs the call.  With
+     tune_cache_path the choice is read at cmif_plan when the file holds it
+     (no timing) and written after timing.  Every candidate gives the same
+     counts; MI may differ in the last bits (summation order).  Ignored for
+     SOFT and the plain schedule */
+  CMIF_FLAG_AUTOTUNE = 1u << 4
 };
 
 /* Plan description.  Every pointer is a host pointer read during cmif_plan
@@ -133,6 +144,15 @@ typedef struct cmif_plan_desc {
   int32_t fallback_capacity; /* FP32_ROUNDED: label pairs per pass that the
                                 FP64 re-run can take, 0 = min(64, pairs per
                                 pass), at most 4096; sizes scratch */
+  const char* tune_cache_path; /* CMIF_FLAG_AUTOTUNE: text file of tuned
+                                  shapes, one line per plan key:
+                                  "cmif-tune v1 gfx950 <Ph>x<Pw>... qa=<Q_A>
+                                  qb=<Q_B> prec=<precision> batch=<angle
+                                  batch> rows_per_wg=<1..8> bpw=<0|4|8|16>
+                                  xcd=<0|1>" (one <Ph>x<Pw> per image pair);
+                                  unreadable or malformed lines are ignored,
+                                  an unwritable file only skips the write;
+                                  NULL = no file */
 } cmif_plan_desc;
 
 typedef struct cmif_plan_s* cmif_plan_t;
@@ -297,7 +317,14 @@ typedef struct cmif_plan_info {
   int32_t graph_captures;     /* launch sequences captured into HIP graphs */
   int32_t graph_replays;      /* calls that replayed a captured graph */
   int32_t fft_h, fft_w;       /* FFT lengths of image pair 0 */
-  int32_t reserved[2];
+  int32_t rows_per_wg;        /* pair row kernel: map rows per workgroup */
+  int32_t labels_per_team;    /* pair row kernel: labels of B per team (0:
+                                 the default shape) */
+  int32_t xcd_grouping;       /* pair column kernel: XCD-grouped order (1)
+                                 or launch order (0, the default) */
+  int32_t tuned;              /* 0 default shapes, 1 timed, 2 from the cache */
+  int32_t tune_runs;          /* eager passes spent timing candidates */
+  int32_t reserved;
 } cmif_plan_info;
 
 /* Fills *info (host memory).  Errors: CMIF_ERR_INVALID_ARGUMENT on NULL. */

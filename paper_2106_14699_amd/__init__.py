@@ -37,6 +37,7 @@ CMIF_FLAG_FORCE_FALLBACK = 1 << 0
 CMIF_FLAG_NO_GRAPH = 1 << 1
 CMIF_FLAG_SAVE_FOR_BACKWARD = 1 << 2
 CMIF_FLAG_PLAIN_SCHEDULE = 1 << 3
+CMIF_FLAG_AUTOTUNE = 1 << 4
 
 EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_compute", "cmif_align", "cmif_backward",
@@ -60,7 +61,8 @@ class cmif_plan_desc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("device", ctypes.c_int32),
                 ("angle_batch", ctypes.c_int32),
-                ("fallback_capacity", ctypes.c_int32)]
+                ("fallback_capacity", ctypes.c_int32),
+                ("tune_cache_path", ctypes.c_char_p)]
 
 
 class cmif_stats(ctypes.Structure):
@@ -96,7 +98,10 @@ class cmif_plan_info(ctypes.Structure):
                 ("graph_captures", ctypes.c_int32),
                 ("graph_replays", ctypes.c_int32),
                 ("fft_h", ctypes.c_int32), ("fft_w", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("rows_per_wg", ctypes.c_int32),
+                ("labels_per_team", ctypes.c_int32),
+                ("xcd_grouping", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("tune_runs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class cmif_stage_time(ctypes.Structure):
@@ -263,7 +268,8 @@ class Plan:
                  q_b: int, angles: Sequence[float] | None = None,
                  gamma: float = 0.5, precision: str = "fp32",
                  mode: str = "hard", flags: int = 0, device: int = 0,
-                 angle_batch: int = 0, fallback_capacity: int = 0):
+                 angle_batch: int = 0, fallback_capacity: int = 0,
+                 tune_cache_path: str | None = None):
         import torch
         self._torch = torch
         self.sizes = [tuple(int(v) for v in s) for s in sizes]
@@ -292,6 +298,9 @@ class Plan:
         d.device = self.device
         d.angle_batch = int(angle_batch)
         d.fallback_capacity = int(fallback_capacity)
+        self._tune_path = (tune_cache_path.encode() if tune_cache_path
+                           else None)
+        d.tune_cache_path = self._tune_path
         self.handle = cmif_plan(d)
         self.persistent_bytes, self.scratch_bytes = cmif_workspace_size(
             self.handle)

@@ -20,6 +20,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -137,6 +139,14 @@ struct cmif_plan_s {
   GraphCache graphs[2];  // [0] cmif_compute, [1] cmif_align
   int graph_captures = 0;
   int graph_replays = 0;
+  // launch shapes (defaults, or the autotuner's choice)
+  int rows_per_wg = 2;   // pair row kernel: map rows per workgroup
+  int bpw = 0;           // pair row kernel: labels of B per team (0: default)
+  int xcd = 0;           // pair column kernel: XCD-grouped order
+  int tuned = 0;         // 0 default, 1 timed, 2 read from the cache
+  int tune_runs = 0;
+  std::string tune_path;
+  std::string tune_key;
 };
 
 namespace {
@@ -372,7 +382,7 @@ cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout&
   pc.tiles = half / tile_width<double>(); pc.nb = nb; pc.Z = z;
   pc.z_angle_stride = (long long)half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh;
-  pc.tw = twiddles<double>(P, pers, g.ph);
+  pc.tw = twiddles<double>(P, pers, g.ph); pc.xcd = P.xcd;
   STAGE(ST_PAIR_COLS, nb * (double)half * (g.ph + g.sh) * sizeof(C64),
         launch_pair_cols<double>(g.ph, pc, st));
   STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(maxn, 0u, nb, st));
@@ -465,7 +475,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pc.QA = qa; pc.QB = qb; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
     pc.tiles = tiles; pc.nb = nb; pc.Z = z;
     pc.z_angle_stride = (long long)qa * qb * half * g.sh;
-    pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h;
+    pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h; pc.xcd = P.xcd;
     // A's spectra once per launch, B's once per angle, every pair's columns
     STAGE(ST_PAIR_COLS,
           (double)qa * half * g.ph * sizeof(CT) +
@@ -498,7 +508,8 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
     pr.QA = qa; pr.QB = qb; pr.wa = g.wa; pr.wb = g.wb;
     pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb; pr.tw = tw_w;
-    pr.logtab = logtab; pr.xlogtab = xlogtab; pr.rows_per_wg = 2;
+    pr.logtab = logtab; pr.xlogtab = xlogtab; pr.rows_per_wg = P.rows_per_wg;
+    pr.bpw = P.bpw;
     pr.mi = mi_ptr; pr.mi_angle_stride = map_stride;
     pr.n = n_ptr; pr.n_angle_stride = map_stride; pr.maxn = maxn; pr.flags = flags;
     pr.stats = stats;
@@ -728,6 +739,156 @@ cmif_status run_pair_plain(cmif_plan_s& P, int p, const uint8_t* la,
   return CMIF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning of the launch shapes (CMIF_FLAG_AUTOTUNE)
+// ---------------------------------------------------------------------------
+
+bool tunable(const cmif_plan_s* P) {
+  return (P->d.flags & CMIF_FLAG_AUTOTUNE) && P->d.mode == CMIF_MODE_HARD &&
+         !(P->d.flags & CMIF_FLAG_PLAIN_SCHEDULE);
+}
+
+std::string tune_key(const cmif_plan_s* P) {
+  std::ostringstream k;
+  k << "cmif-tune v1 gfx950";
+  for (const PairPlan& g : P->pairs) k << " " << g.ph << "x" << g.pw;
+  k << " qa=" << P->d.q_a << " qb=" << P->d.q_b << " prec=" << P->d.precision
+    << " batch=" << P->batch;
+  return k.str();
+}
+
+// Reads "<key> rows_per_wg=R bpw=B xcd=X" lines; true if the key is found.
+bool tune_read(cmif_plan_s* P) {
+  std::ifstream f(P->tune_path);
+  if (!f) return false;
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t at = line.find(" rows_per_wg=");
+    if (at == std::string::npos || line.substr(0, at) != P->tune_key) continue;
+    int r = 0, b = 0, x = 0;
+    if (std::sscanf(line.c_str() + at, " rows_per_wg=%d bpw=%d xcd=%d", &r, &b, &x) != 3)
+      continue;
+    if (r < 1 || r > 8 || (b != 0 && b != 4 && b != 8 && b != 16) || x < 0 || x > 1)
+      continue;
+    P->rows_per_wg = r;
+    P->bpw = b;
+    P->xcd = x;
+    return true;
+  }
+  return false;
+}
+
+void tune_write(const cmif_plan_s* P) {
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(P->tune_path);
+    std::string line;
+    while (f && std::getline(f, line)) {
+      const size_t at = line.find(" rows_per_wg=");
+      if (at != std::string::npos && line.substr(0, at) == P->tune_key) continue;
+      if (!line.empty()) lines.push_back(line);
+    }
+  }
+  std::ostringstream e;
+  e << P->tune_key << " rows_per_wg=" << P->rows_per_wg << " bpw=" << P->bpw
+    << " xcd=" << P->xcd;
+  lines.push_back(e.str());
+  const std::string tmp = P->tune_path + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return;  // the cache is an optimisation: an unwritable path is ignored
+    for (const std::string& l : lines) f << l << "\n";
+  }
+  (void)std::rename(tmp.c_str(), P->tune_path.c_str());
+}
+
+// Stage milliseconds of the recorded launches; clears the records and hands
+// their events back to the pool above `base`.
+cmif_status stage_ms(cmif_plan_s* P, double* ms, size_t base) {
+  for (int s = 0; s < ST_COUNT; ++s) ms[s] = 0.0;
+  for (const ProfRec& r : P->prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, "hipEventSynchronize failed");
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      return fail(CMIF_ERR_DEVICE, "hipEventElapsedTime failed");
+    ms[r.stage] += t;
+  }
+  P->prof.recs.clear();
+  P->prof.used = base;
+  return CMIF_OK;
+}
+
+// Times one eager pass per candidate (the call's own inputs and outputs;
+// no stats), keeps the fastest row shape and column order.  The caller's
+// stage-profiler records are set aside meanwhile.
+template <class F>
+cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
+  if (P->tuned || !tunable(P)) return CMIF_OK;
+  std::vector<ProfRec> saved;
+  saved.swap(P->prof.recs);
+  const bool was_on = P->prof.on;
+  const size_t used0 = P->prof.used;
+  P->prof.on = true;
+  struct Cand { int rpw, bpw, xcd; };
+  std::vector<Cand> cands;
+  const size_t er = P->d.precision == CMIF_PREC_FP64 ? sizeof(double) : sizeof(float);
+  PairRowsConfig def;
+  const bool have_def = pair_rows_config(er, P->pairs[0].pw, P->d.q_b, &def);
+  for (int bpw : {0, 4, 8, 16}) {
+    if (bpw != 0) {
+      bool fits = true;
+      for (const PairPlan& g : P->pairs) {
+        PairRowsConfig c;
+        fits = fits && pair_rows_config_bpw(er, g.pw, P->d.q_b, bpw, &c);
+      }
+      if (!fits || (have_def && def.bpw == bpw)) continue;
+    }
+    for (int rpw : {1, 2, 4}) cands.push_back({rpw, bpw, (int)(cands.size() & 1)});
+  }
+  double best_rows = 1e300, best_cols[2] = {1e300, 1e300};
+  Cand pick{2, 0, 0};
+  // an untimed pass first: code loading and cold caches stay out of the choice
+  cmif_status s = pass(st);
+  if (s == CMIF_OK) {
+    double ms[ST_COUNT];
+    s = stage_ms(P, ms, used0);
+  }
+  for (size_t k = 0; s == CMIF_OK && k < cands.size(); ++k) {
+    const Cand& c = cands[k];
+    P->rows_per_wg = c.rpw;
+    P->bpw = c.bpw;
+    P->xcd = c.xcd;
+    s = pass(st);
+    if (s != CMIF_OK) break;
+    double ms[ST_COUNT];
+    s = stage_ms(P, ms, used0);
+    if (s != CMIF_OK) break;
+    ++P->tune_runs;
+    if (ms[ST_PAIR_ROWS] < best_rows) {
+      best_rows = ms[ST_PAIR_ROWS];
+      pick.rpw = c.rpw;
+      pick.bpw = c.bpw;
+    }
+    best_cols[c.xcd] = std::min(best_cols[c.xcd], ms[ST_PAIR_COLS]);
+  }
+  P->prof.on = was_on;
+  P->prof.recs.swap(saved);
+  P->prof.used = used0;
+  if (s != CMIF_OK) {
+    P->rows_per_wg = 2;
+    P->bpw = 0;
+    P->xcd = 0;
+    return s;
+  }
+  P->rows_per_wg = pick.rpw;
+  P->bpw = pick.bpw;
+  P->xcd = best_cols[0] < best_cols[1] ? 0 : 1;
+  P->tuned = 1;
+  if (!P->tune_path.empty()) tune_write(P);
+  return CMIF_OK;
+}
+
 cmif_status validate_ws(const cmif_plan_s* P, void* pers, size_t pers_bytes,
                         void* scr, size_t scr_bytes) {
   if (pers_bytes < P->persistent_bytes || scr_bytes < P->scratch_bytes)
@@ -879,6 +1040,7 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
   pc.tiles = tiles; pc.nb = 1; pc.Z = z;
   pc.z_angle_stride = (long long)qa * qb * half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh; pc.tw = twiddles<T>(P, pers, g.ph);
+  pc.xcd = P.xcd;
   const double zbytes = (double)qa * qb * half * g.sh * sizeof(CT);
   STAGE(ST_PAIR_COLS,
         (double)(qa + qb) * half * g.ph * sizeof(CT) + zbytes,
@@ -1052,6 +1214,11 @@ cmif_status cmif_plan_query(cmif_plan_t plan, cmif_plan_info* info) {
   info->graph_replays = plan->graph_replays;
   info->fft_h = plan->pairs[0].ph;
   info->fft_w = plan->pairs[0].pw;
+  info->rows_per_wg = plan->rows_per_wg;
+  info->labels_per_team = plan->bpw;
+  info->xcd_grouping = plan->xcd;
+  info->tuned = plan->tuned;
+  info->tune_runs = plan->tune_runs;
   return CMIF_OK;
 }
 
@@ -1111,7 +1278,8 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   if (d->mode != CMIF_MODE_HARD && d->mode != CMIF_MODE_SOFT)
     return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown mode");
   const uint32_t known = CMIF_FLAG_FORCE_FALLBACK | CMIF_FLAG_NO_GRAPH |
-                         CMIF_FLAG_SAVE_FOR_BACKWARD | CMIF_FLAG_PLAIN_SCHEDULE;
+                         CMIF_FLAG_SAVE_FOR_BACKWARD | CMIF_FLAG_PLAIN_SCHEDULE |
+                         CMIF_FLAG_AUTOTUNE;
   if (d->flags & ~known) return fail(CMIF_ERR_INVALID_ARGUMENT, "unknown flags");
   if ((d->flags & CMIF_FLAG_PLAIN_SCHEDULE) &&
       (d->mode != CMIF_MODE_HARD || d->precision != CMIF_PREC_FP64))
@@ -1138,6 +1306,8 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   P->d = *d;
   P->d.h_a = P->d.w_a = P->d.h_b = P->d.w_b = nullptr;
   P->d.angles_rad = nullptr;
+  if (d->tune_cache_path) P->tune_path = d->tune_cache_path;
+  P->d.tune_cache_path = nullptr;
   for (int p = 0; p < d->n_pairs; ++p) {
     PairPlan g{};
     g.ha = d->h_a[p]; g.wa = d->w_a[p]; g.hb = d->h_b[p]; g.wb = d->w_b[p];
@@ -1222,6 +1392,10 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   size_t smax = 0;
   for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);
   P->scratch_bytes = smax;
+  if (tunable(P)) {
+    P->tune_key = tune_key(P);
+    if (!P->tune_path.empty() && tune_read(P)) P->tuned = 2;
+  }
   *out = P;
   return CMIF_OK;
 }
@@ -1260,6 +1434,10 @@ cmif_status cmif_compute(cmif_plan_t plan, const cmif_inputs* in,
   auto body = [&](hipStream_t s) {
     return run_calls(plan, in, out, best, per_angle, stats, persistent, scratch, s);
   };
+  s = autotune(plan, st, [&](hipStream_t s2) {
+    return run_calls(plan, in, out, best, per_angle, nullptr, persistent, scratch, s2);
+  });
+  if (s != CMIF_OK) return s;
   if (!graph_allowed(plan)) return body(st);
   return run_graph(plan, 0,
                    call_key(plan, 0, in, out, best, per_angle, stats, persistent,
@@ -1289,6 +1467,11 @@ cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
     return run_calls(plan, in, nullptr, best, per_angle, stats, persistent,
                      scratch, s);
   };
+  s = autotune(plan, st, [&](hipStream_t s2) {
+    return run_calls(plan, in, nullptr, best, per_angle, nullptr, persistent,
+                     scratch, s2);
+  });
+  if (s != CMIF_OK) return s;
   if (!graph_allowed(plan)) return body(st);
   return run_graph(plan, 1,
                    call_key(plan, 1, in, nullptr, best, per_angle, stats,

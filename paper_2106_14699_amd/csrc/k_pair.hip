@@ -229,7 +229,8 @@ static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
                                      (int)shm);
   if (e != hipSuccess) return e;
   dim3 grid = a.items ? dim3(a.tiles, a.max_items, 1) : dim3(a.tiles, a.QA, a.nb);
-  const int xcd_groups = !a.items && ((long long)a.tiles * a.nb) % 8 == 0;
+  const int xcd_groups =
+      !a.items && a.xcd != 0 && ((long long)a.tiles * a.nb) % 8 == 0;
   hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.FA, a.fa_label_stride,
                      a.FB, a.fb_angle_stride, a.fb_label_stride, a.QB, a.ha,
                      a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw,

@@ -426,7 +426,9 @@ static hipError_t launch_pr_bpw(const PairRowsArgs<T>& a, const PairRowsConfig& 
 template <typename T, int P>
 hipError_t launch_pair_rows_p(const PairRowsArgs<T>& a, hipStream_t st) {
   PairRowsConfig c;
-  if (!pair_rows_config(sizeof(T), P, a.QB, &c)) return hipErrorInvalidValue;
+  const bool ok = a.bpw > 0 ? pair_rows_config_bpw(sizeof(T), P, a.QB, a.bpw, &c)
+                            : pair_rows_config(sizeof(T), P, a.QB, &c);
+  if (!ok) return hipErrorInvalidValue;
   if (c.bpw == 4) return launch_pr_bpw<T, P, 4>(a, c, st);
   if (c.bpw == 8) return launch_pr_bpw<T, P, 8>(a, c, st);
   return launch_pr_bpw<T, P, 16>(a, c, st);

@@ -53,6 +53,7 @@ struct PairColsArgs {
   const int4* items;
   const uint32_t* n_items;  // device count of valid items
   int max_items;            // grid size in item mode
+  int xcd;                  // XCD-grouped workgroup order: 0 off, 1 on
 };
 
 template <typename T>
@@ -64,6 +65,7 @@ struct PairRowsArgs {
   const double* logtab;  // 512 entries: log2(1 + j/256), 1/(1 + j/256)
   const double* xlogtab; // kXlogN entries: c log2 c
   int rows_per_wg;       // map rows handled by one workgroup
+  int bpw;               // labels of B per team, 0 = pair_rows_config's choice
   double* mi;            // nullable, [nb][sh][sw]
   long long mi_angle_stride;
   int32_t* n;            // nullable, [nb][sh][sw]
@@ -212,6 +214,22 @@ inline bool pair_rows_config(size_t elem_real, int P, int QB, PairRowsConfig* c)
     return true;
   }
   return false;
+}
+
+// The shape for a given bpw (4, 8 or 16); false if it does not fit.
+inline bool pair_rows_config_bpw(size_t elem_real, int P, int QB, int bpw,
+                                 PairRowsConfig* c) {
+  const int team = team_for(P);
+  const int nteams = (QB + bpw - 1) / bpw;
+  const int nt = nteams * team;
+  if (nt > 1024 || (bpw != 4 && bpw != 8 && bpw != 16)) return false;
+  const size_t lds = pair_rows_lds(elem_real, P, nteams);
+  if (lds > 160 * 1024) return false;
+  c->bpw = bpw;
+  c->nteams = nteams;
+  c->ntmax = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
+  c->lds = lds;
+  return true;
 }
 
 // Block shape of the soft row kernel (bpw 4 or 8, double accumulators).

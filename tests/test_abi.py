@@ -248,6 +248,45 @@ def test_plain_schedule_plans(cm):
     assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
 
 
+def _tune_plan(cm, path, flags=None, mode=0):
+    d = make_desc(cm, sizes=((64, 64, 64, 64),), qa=4, qb=4)
+    d.flags = cm.CMIF_FLAG_AUTOTUNE if flags is None else flags
+    d.mode = mode
+    keep = path.encode() if path else None
+    d.tune_cache_path = keep
+    h = cm.cmif_plan(d)
+    try:
+        return cm.cmif_plan_query(h)
+    finally:
+        cm.cmif_plan_free(h)
+
+
+def test_autotune_plan_and_cache_file(cm, tmp_path):
+    # no file: default shapes, not yet tuned
+    info = _tune_plan(cm, None)
+    assert (info["tuned"], info["tune_runs"]) == (0, 0)
+    assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
+        == (2, 0, 0)
+    ph, pw = info["fft_h"], info["fft_w"]
+    key = f"cmif-tune v1 gfx950 {ph}x{pw} qa=4 qb=4 prec=0 batch={info['angle_batch']}"
+    f = tmp_path / "tune.txt"
+    # a missing file, then malformed or out-of-range lines, are ignored
+    assert _tune_plan(cm, str(f))["tuned"] == 0
+    f.write_text("garbage\n" + key + " rows_per_wg=9 bpw=4 xcd=0\n"
+                 + key + " rows_per_wg=1 bpw=5 xcd=0\n"
+                 + key.replace("qa=4", "qa=3") + " rows_per_wg=4 bpw=8 xcd=0\n")
+    assert _tune_plan(cm, str(f))["tuned"] == 0
+    # a matching line is taken at plan time (no timing on the first call)
+    f.write_text(f.read_text() + key + " rows_per_wg=4 bpw=8 xcd=0\n")
+    info = _tune_plan(cm, str(f))
+    assert info["tuned"] == 2 and info["tune_runs"] == 0
+    assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
+        == (4, 8, 0)
+    # without the flag, or for SOFT, the file is not consulted
+    assert _tune_plan(cm, str(f), flags=0)["tuned"] == 0
+    assert _tune_plan(cm, str(f), mode=cm.CMIF_MODE_SOFT)["tuned"] == 0
+
+
 def test_status_strings(cm):
     seen = set()
     for s in range(8):

@@ -1,0 +1,94 @@
+"""GPU: the launch-shape autotuner (CMIF_FLAG_AUTOTUNE).
+
+The first call of a tuned plan times every candidate shape of the pair row
+and column kernels on its own buffers, keeps the fastest, and writes the
+choice to the cache file; a second plan with the same file reads it at plan
+time and times nothing.  Counts, digests and N must match the default
+shapes bit for bit, MI to the summation-order tolerance, and the oracle at
+sampled displacements of one angle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import MI_TOL, dev, say
+
+pytestmark = pytest.mark.gpu
+
+FORCE = 1 << 0
+AUTOTUNE = 1 << 4
+
+
+def _run(plan, ins):
+    return plan.compute(*ins, mi=True, n=True, counts=True, digest=True,
+                        best=True, per_angle=True)
+
+
+def _same(r, ref):
+    for name in ("n", "counts", "digest"):
+        g = r[name][0].cpu().numpy()
+        e = ref[name][0].cpu().numpy()
+        assert np.array_equal(g.view(np.uint8), e.view(np.uint8)), name
+    err = np.abs(r["mi"][0].cpu().numpy() - ref["mi"][0].cpu().numpy()).max()
+    assert err <= MI_TOL, err
+    return err
+
+
+@pytest.mark.parametrize("size,q,prec,flags", [
+    ((100, 90, 80, 110), (4, 12), "fp32", 0),
+    ((100, 90, 80, 110), (4, 12), "fp32", FORCE),
+    ((300, 260, 280, 310), (8, 8), "fp32", 0),
+    ((160, 150, 170, 140), (6, 5), "fp64", 0),
+], ids=["fp32-q4x12", "fp32-forced-rerun", "fp32-p1024", "fp64"])
+def test_tuned_plan_matches_default(gpu, oracle, tmp_path, size, q, prec, flags):
+    cm, torch = gpu
+    ha, wa, hb, wb = size
+    qa, qb = q
+    angles = [0.0, math.radians(40.0), math.radians(250.0)]
+    c = synth.random_case(710 + qa, ha, wa, hb, wb, qa, qb, mask_density=0.8)
+    ins = [dev(torch, c[k]) for k in ("A", "MA", "B", "MB")]
+    cache = str(tmp_path / "tune.txt")
+    say(f"[gpu] autotune {size} q={q} {prec} flags={flags}")
+    base = cm.Plan([size], qa, qb, angles=angles, precision=prec, flags=flags)
+    ref = _run(base, ins)
+    tuned = cm.Plan([size], qa, qb, angles=angles, precision=prec,
+                    flags=flags | AUTOTUNE, tune_cache_path=cache)
+    assert tuned.info()["tuned"] == 0
+    r1 = _run(tuned, ins)
+    info = tuned.info()
+    say(f"tuned info {info}")
+    assert info["tuned"] == 1 and info["tune_runs"] >= 3
+    assert info["rows_per_wg"] in (1, 2, 4)
+    assert info["labels_per_team"] in (0, 4, 8, 16)
+    assert info["xcd_grouping"] in (0, 1)
+    err = _same(r1, ref)
+    assert r1["best"] == ref["best"] or err > 0.0
+    # later calls (graph capture, then replay) with the chosen shapes
+    for _ in range(2):
+        _same(_run(tuned, ins), ref)
+    assert tuned.info()["tune_runs"] == info["tune_runs"]
+    # the cache file now holds the choice; a new plan times nothing
+    again = cm.Plan([size], qa, qb, angles=angles, precision=prec,
+                    flags=flags | AUTOTUNE, tune_cache_path=cache)
+    i2 = again.info()
+    assert i2["tuned"] == 2 and i2["tune_runs"] == 0
+    assert (i2["rows_per_wg"], i2["labels_per_team"], i2["xcd_grouping"]) == \
+        (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"])
+    r2 = _run(again, ins)
+    assert again.info()["tune_runs"] == 0
+    _same(r2, ref)
+    # sampled displacements of one angle against the oracle
+    bw, mw = oracle.warp_nn(c["B"], c["MB"], angles[1])
+    mi = r2["mi"][0][1].cpu().numpy()
+    n = r2["n"][0][1].cpu().numpy()
+    cnt = r2["counts"][0][1].cpu().numpy()
+    rng = np.random.default_rng(3)
+    sh, sw = mi.shape
+    for _ in range(24):
+        i, j = int(rng.integers(sh)), int(rng.integers(sw))
+        mo, no, jo = oracle.cmif_at(c["A"], c["MA"], bw, mw, qa, qb,
+                                    i - (ha - 1), j - (wa - 1))
+        assert n[i, j] == no and np.array_equal(cnt[:, :, i, j], jo), (i, j)
+        assert abs(mi[i, j] - mo) <= MI_TOL, (i, j)
