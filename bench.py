@@ -153,6 +153,9 @@ def main():
                     help="skip the soft-membership batch")
     ap.add_argument("--soft-steps", type=int, default=5)
     ap.add_argument("--copy-gib", type=float, default=0.0)
+    ap.add_argument("--tune-cache", default=None,
+                    help="text file of tuned launch shapes: read at plan time "
+                         "when it holds this workload, written after tuning")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing "
                          "the candidates in the warm-up call "
@@ -178,7 +181,8 @@ def main():
     A, MA, B, MB = dev(c["A"]), dev(c["MA"]), dev(c["B"]), dev(c["MB"])
     plan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
                    gamma=c["gamma"], precision="fp32",
-                   flags=0 if args.no_autotune else cm.CMIF_FLAG_AUTOTUNE)
+                   flags=0 if args.no_autotune else cm.CMIF_FLAG_AUTOTUNE,
+                   tune_cache_path=args.tune_cache)
     n_maps = len(c["angles"])
 
     # warm-up: the first call captures the launch graph the timed steps replay
