@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-soft", action="store_true",
                     help="skip the soft-membership batch")
     ap.add_argument("--soft-steps", type=int, default=5)
+    ap.add_argument("--no-window", action="store_true",
+                    help="skip the windowed sweep (Alg. 1's padded window)")
     ap.add_argument("--copy-gib", type=float, default=0.0)
     ap.add_argument("--tune-cache", default=None,
                     help="text file of tuned launch shapes: read at plan time "
@@ -266,6 +268,36 @@ def main():
                      (best["angle_index"], best["dy"], best["dx"]))
         del pplan
 
+    window = None
+    if not args.no_window:
+        # Alg. 1's padded search window for gamma = 0.5: |chi| <= H_B (1 - gamma)
+        # per axis; only those 513 x 513 displacements are stored and reduced
+        r = int(math.ceil(n * (1.0 - c["gamma"])))
+        print(f"[bench] windowed sweep +-{r}", file=sys.stderr, flush=True)
+        wplan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
+                        gamma=c["gamma"], precision="fp32",
+                        flags=0 if args.no_autotune else cm.CMIF_FLAG_AUTOTUNE,
+                        tune_cache_path=args.tune_cache,
+                        windows=[(-r, r, -r, r)])
+        wplan.align(A, MA, B, MB)
+        torch.cuda.synchronize()
+        we = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        we[0].record()
+        for k in range(args.steps):
+            wout = wplan.align(A, MA, B, MB, sync=False)
+            we[k + 1].record()
+        torch.cuda.synchronize()
+        wms = we[0].elapsed_time(we[-1]) / args.steps
+        wb = cm.best_from_bytes(bytes(wout["best_raw"][0].cpu().numpy()))
+        winfo = wplan.info()
+        window = dict(window=[-r, r, -r, r], map=[2 * r + 1, 2 * r + 1],
+                      fft=[winfo["fft_h"], winfo["fft_w"]],
+                      ms_per_step=round(wms, 3),
+                      value=round(n_maps * 1000.0 / wms, 2), unit="maps/s",
+                      same_best=(wb["angle_index"], wb["dy"], wb["dx"]) ==
+                      (best["angle_index"], best["dy"], best["dx"]))
+        del wplan
+
     soft = None
     if not args.no_soft:
         print("[bench] soft batch", file=sys.stderr, flush=True)
@@ -320,6 +352,7 @@ def main():
         "speedup_vs_plain_fp64": (round(plain["ms_per_step_median"] /
                                         float(np.median(step_ms)), 3)
                                   if plain else None),
+        "window_sweep": window,
         "soft": soft,
         "launch_shapes": {k: info1[k] for k in ("rows_per_wg", "labels_per_team",
                                                 "xcd_grouping", "tuned",

@@ -21,10 +21,13 @@
  * Conventions that every entry point shares:
  *   - Images are row-major, uint8 labels in [0, Q) wherever their mask is
  *     set; masks are uint8 0/1 (a NULL mask means all ones).
- *   - Displacements: the full set of chi with a non-empty rectangle overlap,
- *     chi_y in [-(h_a-1), h_b-1], chi_x in [-(w_a-1), w_b-1].  A map has
- *     S_h x S_w entries, S_h = h_a + h_b - 1, S_w = w_a + w_b - 1, and entry
- *     [i][j] holds chi = (i - (h_a-1), j - (w_a-1)).
+ *   - Displacements: by default the full set of chi with a non-empty
+ *     rectangle overlap, chi_y in [-(h_a-1), h_b-1], chi_x in [-(w_a-1),
+ *     w_b-1]; a plan may restrict each image pair to a window [y0, y1] x
+ *     [x0, x1] inside that set (the padded search window of Alg. 1).  A map
+ *     has S_h x S_w entries, S_h = y1 - y0 + 1, S_w = x1 - x0 + 1 (full set:
+ *     h_a + h_b - 1 and w_a + w_b - 1, y0 = -(h_a-1), x0 = -(w_a-1)), and
+ *     entry [i][j] holds chi = (y0 + i, x0 + j).
  *   - Marginal counts and N are the exact integer sums of the rounded joint
  *     counts (identical to Eq. 10-11 in exact arithmetic).
  *   - MI is in bits, 0 where N = 0, with 0 log 0 = 0.
@@ -146,13 +149,27 @@ typedef struct cmif_plan_desc {
                                 pass), at most 4096; sizes scratch */
   const char* tune_cache_path; /* CMIF_FLAG_AUTOTUNE: text file of tuned
                                   shapes, one line per plan key:
-                                  "cmif-tune v1 gfx950 <Ph>x<Pw>... qa=<Q_A>
-                                  qb=<Q_B> prec=<precision> batch=<angle
-                                  batch> rows_per_wg=<1..8> bpw=<0|4|8|16>
-                                  xcd=<0|1>" (one <Ph>x<Pw> per image pair);
+                                  "cmif-tune v1 gfx950 <Ph>x<Pw>:<S_h>x<S_w>...
+                                  qa=<Q_A> qb=<Q_B> prec=<precision>
+                                  batch=<angle batch> rows_per_wg=<1..8>
+                                  bpw=<0|4|8|16> xcd=<0|1>" (FFT and map
+                                  sizes of each image pair);
                                   unreadable or malformed lines are ignored,
                                   an unwritable file only skips the write;
                                   NULL = no file */
+  const int32_t* window;     /* [n_pairs][4] displacement windows y0, y1,
+                                x0, x1 (inclusive), each inside the full
+                                set: -(h_a-1) <= y0 <= y1 <= h_b-1 and the
+                                same for x; NULL = the full set for every
+                                pair.  Maps, counts, digests, N, the gamma
+                                threshold (gamma * max N over the window)
+                                and the argmax cover the window only, and
+                                the FFT side per axis is the smallest power
+                                of two >= max(y1 + h_a, h_b - y0) (>= 128),
+                                the least that keeps the window free of
+                                circular aliasing.  HARD mode, fused
+                                schedule only (otherwise
+                                CMIF_ERR_UNSUPPORTED) */
 } cmif_plan_desc;
 
 typedef struct cmif_plan_s* cmif_plan_t;
@@ -213,13 +230,14 @@ typedef struct cmif_outputs {
 } cmif_outputs;
 
 /* Builds a plan: validates the description, chooses FFT sizes (smallest
-   power of two >= S per axis, at least 128), workspace layout and angle
-   batching, and computes the fixed-point rotation coefficients.  Touches no
-   device memory.  On success *out owns host memory released by
-   cmif_plan_free.  Errors: CMIF_ERR_INVALID_ARGUMENT (NULL desc/out/size
-   arrays, n_pairs < 1, sizes out of range, Q out of range, gamma outside
-   [0, 1] or NaN, unknown precision/mode/flags), CMIF_ERR_UNSUPPORTED,
-   CMIF_ERR_NO_DEVICE, CMIF_ERR_HOST_MEMORY. */
+   power of two >= S per axis, at least 128; with a window the alias-free
+   size of the window), workspace layout and angle batching, and computes
+   the fixed-point rotation coefficients.  Touches no device memory.  On
+   success *out owns host memory released by cmif_plan_free.  Errors:
+   CMIF_ERR_INVALID_ARGUMENT (NULL desc/out/size arrays, n_pairs < 1, sizes
+   out of range, Q out of range, gamma outside [0, 1] or NaN, unknown
+   precision/mode/flags, a window not inside the full set or empty),
+   CMIF_ERR_UNSUPPORTED, CMIF_ERR_NO_DEVICE, CMIF_ERR_HOST_MEMORY. */
 cmif_status cmif_plan(const cmif_plan_desc* desc, cmif_plan_t* out);
 
 /* Releases host state; never frees caller memory.  NULL is ignored. */

@@ -62,7 +62,8 @@ class cmif_plan_desc(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("device", ctypes.c_int32),
                 ("angle_batch", ctypes.c_int32),
                 ("fallback_capacity", ctypes.c_int32),
-                ("tune_cache_path", ctypes.c_char_p)]
+                ("tune_cache_path", ctypes.c_char_p),
+                ("window", ctypes.POINTER(ctypes.c_int32))]
 
 
 class cmif_stats(ctypes.Structure):
@@ -269,7 +270,8 @@ class Plan:
                  gamma: float = 0.5, precision: str = "fp32",
                  mode: str = "hard", flags: int = 0, device: int = 0,
                  angle_batch: int = 0, fallback_capacity: int = 0,
-                 tune_cache_path: str | None = None):
+                 tune_cache_path: str | None = None,
+                 windows: Sequence[tuple[int, int, int, int]] | None = None):
         import torch
         self._torch = torch
         self.sizes = [tuple(int(v) for v in s) for s in sizes]
@@ -301,6 +303,15 @@ class Plan:
         self._tune_path = (tune_cache_path.encode() if tune_cache_path
                            else None)
         d.tune_cache_path = self._tune_path
+        # displacement windows (y0, y1, x0, x1) per pair; None = full set
+        self.windows = None if windows is None else [
+            tuple(int(v) for v in w) for w in windows]
+        if self.windows is not None:
+            if len(self.windows) != n:
+                raise ValueError("one window per image pair")
+            win = (ctypes.c_int32 * (4 * n))(*[v for w in self.windows for v in w])
+            self._keep.append(win)
+            d.window = ctypes.cast(win, ctypes.POINTER(ctypes.c_int32))
         self.handle = cmif_plan(d)
         self.persistent_bytes, self.scratch_bytes = cmif_workspace_size(
             self.handle)
@@ -312,9 +323,17 @@ class Plan:
             cmif_plan_free(h)
             self.handle = None
 
-    def map_shape(self, p: int = 0):
+    def window(self, p: int = 0):
+        """Displacement window (y0, y1, x0, x1) of pair p: map entry [i][j]
+        holds chi = (y0 + i, x0 + j)."""
+        if self.windows is not None:
+            return self.windows[p]
         ha, wa, hb, wb = self.sizes[p]
-        return ha + hb - 1, wa + wb - 1
+        return 1 - ha, hb - 1, 1 - wa, wb - 1
+
+    def map_shape(self, p: int = 0):
+        y0, y1, x0, x1 = self.window(p)
+        return y1 - y0 + 1, x1 - x0 + 1
 
     def _aligned(self, nbytes: int):
         torch = self._torch

@@ -47,8 +47,13 @@ int pow2_at_least(int v) {
   return p;
 }
 
+// Geometry of one image pair: image sides, map size (the displacement
+// window), FFT sides, and the window's extents on either side of zero
+// (e_a = 1 - y0, e_b = y1 + 1; the image sides for the full set), which the
+// kernels take wherever they map circular lags to map rows and columns.
 struct PairPlan {
   int ha, wa, hb, wb, sh, sw, ph, pw;
+  int eha, ehb, ewa, ewb;
 };
 
 struct ScratchLayout {
@@ -378,7 +383,7 @@ cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout&
   pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
   pc.FB = fb; pc.fb_angle_stride = (long long)half * g.ph;
   pc.fb_label_stride = (long long)half * g.ph;
-  pc.QA = 1; pc.QB = 1; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+  pc.QA = 1; pc.QB = 1; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
   pc.tiles = half / tile_width<double>(); pc.nb = nb; pc.Z = z;
   pc.z_angle_stride = (long long)half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh;
@@ -389,7 +394,7 @@ cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout&
   STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(flags, 0u, nb, st));
   PairRowsArgs<double> pr{};
   pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
-  pr.QA = 1; pr.QB = 1; pr.wa = g.wa; pr.wb = g.wb;
+  pr.QA = 1; pr.QB = 1; pr.wa = g.ewa; pr.wb = g.ewb;
   pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb;
   pr.tw = twiddles<double>(P, pers, g.pw);
   pr.logtab = reinterpret_cast<const double*>(pers + P.logtab_off);
@@ -472,7 +477,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
     pc.FB = fb; pc.fb_angle_stride = (long long)qb * half * g.ph;
     pc.fb_label_stride = (long long)half * g.ph;
-    pc.QA = qa; pc.QB = qb; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+    pc.QA = qa; pc.QB = qb; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
     pc.tiles = tiles; pc.nb = nb; pc.Z = z;
     pc.z_angle_stride = (long long)qa * qb * half * g.sh;
     pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h; pc.xcd = P.xcd;
@@ -487,7 +492,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     if (soft) {
       SoftRowsArgs<T> sr{};
       sr.Z = z; sr.z_angle_stride = pc.z_angle_stride; sr.z_pair_stride = pc.z_pair_stride;
-      sr.QA = qa; sr.QB = qb; sr.wa = g.wa; sr.wb = g.wb; sr.sh = g.sh; sr.sw = g.sw;
+      sr.QA = qa; sr.QB = qb; sr.wa = g.ewa; sr.wb = g.ewb; sr.sh = g.sh; sr.sw = g.sw;
       sr.ph = g.ph; sr.nb = nb; sr.tw = tw_w;
       sr.mi = mi_ptr; sr.mi_angle_stride = map_stride;
       const bool save = (P.d.flags & CMIF_FLAG_SAVE_FOR_BACKWARD) != 0;
@@ -506,7 +511,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     }
     PairRowsArgs<T> pr{};
     pr.Z = z; pr.z_angle_stride = pc.z_angle_stride; pr.z_pair_stride = pc.z_pair_stride;
-    pr.QA = qa; pr.QB = qb; pr.wa = g.wa; pr.wb = g.wb;
+    pr.QA = qa; pr.QB = qb; pr.wa = g.ewa; pr.wb = g.ewb;
     pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb; pr.tw = tw_w;
     pr.logtab = logtab; pr.xlogtab = xlogtab; pr.rows_per_wg = P.rows_per_wg;
     pr.bpw = P.bpw;
@@ -521,7 +526,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     if (!soft && (o.counts || o.digest)) {
       PairCountsArgs<T> pk{};
       pk.Z = z; pk.z_angle_stride = pc.z_angle_stride; pk.z_pair_stride = pc.z_pair_stride;
-      pk.QA = qa; pk.QB = qb; pk.wa = g.wa; pk.wb = g.wb; pk.sh = g.sh; pk.sw = g.sw;
+      pk.QA = qa; pk.QB = qb; pk.wa = g.ewa; pk.wb = g.ewb; pk.sh = g.sh; pk.sw = g.sw;
       pk.ph = g.ph; pk.nb = nb; pk.tw = tw_w;
       pk.counts = o.counts ? o.counts + (long long)a0 * qa * qb * map_stride : nullptr;
       pk.counts_angle_stride = (long long)qa * qb * map_stride;
@@ -565,7 +570,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
       qc.FA = fa64; qc.fa_label_stride = (long long)half * g.ph;
       qc.FB = fb64; qc.fb_angle_stride = (long long)qb * half * g.ph;
       qc.fb_label_stride = (long long)half * g.ph;
-      qc.QA = qa; qc.QB = qb; qc.ha = g.ha; qc.hb = g.hb; qc.sh = g.sh;
+      qc.QA = qa; qc.QB = qb; qc.ha = g.eha; qc.hb = g.ehb; qc.sh = g.sh;
       qc.tiles = tiles64; qc.nb = nb; qc.Z = z64; qc.z_angle_stride = 0;
       qc.z_pair_stride = (long long)half * g.sh;
       qc.tw = twiddles<double>(P, pers, g.ph);
@@ -573,7 +578,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
       STAGE(ST_FB_PAIR, 0.0, launch_pair_cols<double>(g.ph, qc, st));
       PairCountsArgs<double> qk{};
       qk.Z = z64; qk.z_angle_stride = 0; qk.z_pair_stride = qc.z_pair_stride;
-      qk.QA = qa; qk.QB = qb; qk.wa = g.wa; qk.wb = g.wb; qk.sh = g.sh;
+      qk.QA = qa; qk.QB = qb; qk.wa = g.ewa; qk.wb = g.ewb; qk.sh = g.sh;
       qk.sw = g.sw; qk.ph = g.ph; qk.nb = 1;
       qk.tw = twiddles<double>(P, pers, g.pw);
       qk.counts = o.counts ? o.counts + (long long)a0 * qa * qb * map_stride : nullptr;
@@ -596,7 +601,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
       STAGE(ST_ARGMAX, nb * 12.0 * g.sh * g.sw, launch_argmax(am, st));
       ArgmaxFinalArgs af{};
       af.partial = partial; af.nb = nb; af.nchunks = nchunks; af.sw = g.sw;
-      af.ha = g.ha; af.wa = g.wa; af.angle0 = a0;
+      af.ha = g.eha; af.wa = g.ewa; af.angle0 = a0;
       for (int b = 0; b < nb; ++b) af.angles[b] = P.angles[a0 + b];
       af.per_angle = o.per_angle; af.running = running;
       af.first_batch = a0 == 0; af.best_out = o.best;
@@ -657,7 +662,7 @@ cmif_status run_pair_plain(cmif_plan_s& P, int p, const uint8_t* la,
           launch_plain_product(f1, f2, y, half, g.ph, st));
     PairColsArgs<double> pc{};
     pc.FA = nullptr; pc.FB = y; pc.fb_angle_stride = 0; pc.fb_label_stride = fstride;
-    pc.QA = 1; pc.QB = 1; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+    pc.QA = 1; pc.QB = 1; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
     pc.tiles = half / tile_width<double>(); pc.nb = 1; pc.Z = z;
     pc.z_angle_stride = 0; pc.z_pair_stride = (long long)half * g.sh;
     pc.tw = twiddles<double>(P, pers, g.ph);
@@ -665,7 +670,7 @@ cmif_status run_pair_plain(cmif_plan_s& P, int p, const uint8_t* la,
           launch_pair_cols<double>(g.ph, pc, st));
     PairCountsArgs<double> pk{};
     pk.Z = z; pk.z_angle_stride = 0; pk.z_pair_stride = pc.z_pair_stride;
-    pk.QA = 1; pk.QB = 1; pk.wa = g.wa; pk.wb = g.wb; pk.sh = g.sh; pk.sw = g.sw;
+    pk.QA = 1; pk.QB = 1; pk.wa = g.ewa; pk.wb = g.ewb; pk.sh = g.sh; pk.sw = g.sw;
     pk.ph = g.ph; pk.nb = 1; pk.tw = twiddles<double>(P, pers, g.pw);
     pk.values = out; pk.counts_angle_stride = S;
     STAGE(ST_PLAIN, (double)half * g.sh * sizeof(C64) + 8.0 * S,
@@ -722,7 +727,7 @@ cmif_status run_pair_plain(cmif_plan_s& P, int p, const uint8_t* la,
       STAGE(ST_ARGMAX, 12.0 * S, launch_argmax(am, st));
       ArgmaxFinalArgs af{};
       af.partial = partial; af.nb = 1; af.nchunks = nchunks; af.sw = g.sw;
-      af.ha = g.ha; af.wa = g.wa; af.angle0 = ang;
+      af.ha = g.eha; af.wa = g.ewa; af.angle0 = ang;
       af.angles[0] = P.angles[ang];
       af.per_angle = o.per_angle; af.running = running;
       af.first_batch = ang == 0; af.best_out = o.best;
@@ -751,7 +756,8 @@ bool tunable(const cmif_plan_s* P) {
 std::string tune_key(const cmif_plan_s* P) {
   std::ostringstream k;
   k << "cmif-tune v1 gfx950";
-  for (const PairPlan& g : P->pairs) k << " " << g.ph << "x" << g.pw;
+  for (const PairPlan& g : P->pairs)
+    k << " " << g.ph << "x" << g.pw << ":" << g.sh << "x" << g.sw;
   k << " qa=" << P->d.q_a << " qb=" << P->d.q_b << " prec=" << P->d.precision
     << " batch=" << P->batch;
   return k.str();
@@ -1036,7 +1042,7 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
   pc.FA = fa; pc.fa_label_stride = (long long)half * g.ph;
   pc.FB = fb; pc.fb_angle_stride = (long long)qb * half * g.ph;
   pc.fb_label_stride = (long long)half * g.ph;
-  pc.QA = qa; pc.QB = qb; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
+  pc.QA = qa; pc.QB = qb; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
   pc.tiles = tiles; pc.nb = 1; pc.Z = z;
   pc.z_angle_stride = (long long)qa * qb * half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh; pc.tw = twiddles<T>(P, pers, g.ph);
@@ -1047,7 +1053,7 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
         launch_pair_cols<T>(g.ph, pc, st));
   SoftGradRowsArgs<T> gr{};
   gr.Z = z; gr.z_pair_stride = pc.z_pair_stride; gr.QA = qa; gr.QB = qb;
-  gr.wa = g.wa; gr.wb = g.wb; gr.sh = g.sh; gr.sw = g.sw; gr.ph = g.ph;
+  gr.wa = g.ewa; gr.wb = g.ewb; gr.sh = g.sh; gr.sw = g.sw; gr.ph = g.ph;
   gr.tw = twiddles<T>(P, pers, g.pw); gr.grad_mi = grad_mi; gr.save = save;
   gr.ZG = zg;
   STAGE(ST_SOFT_GRAD,
@@ -1057,7 +1063,7 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
   gc.xrow = zg; gc.H = g.sh; gc.tiles = tiles; gc.Q = qa * qb; gc.nb = 1;
   gc.x_angle_stride = 0; gc.x_label_stride = (long long)half * g.sh;
   gc.F = gh; gc.f_angle_stride = 0; gc.f_label_stride = (long long)half * g.ph;
-  gc.tw = twiddles<T>(P, pers, g.ph); gc.circ_ha = g.ha; gc.circ_hb = g.hb;
+  gc.tw = twiddles<T>(P, pers, g.ph); gc.circ_ha = g.eha; gc.circ_hb = g.ehb;
   STAGE(ST_SOFT_GRAD, zbytes + (double)qa * qb * half * g.ph * sizeof(CT),
         launch_fwd_cols<T>(g.ph, gc, st));
   for (int side = 0; side < 2; ++side) {
@@ -1284,6 +1290,9 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   if ((d->flags & CMIF_FLAG_PLAIN_SCHEDULE) &&
       (d->mode != CMIF_MODE_HARD || d->precision != CMIF_PREC_FP64))
     return fail(CMIF_ERR_UNSUPPORTED, "the plain schedule is HARD and FP64 only");
+  if (d->window && (d->mode != CMIF_MODE_HARD || (d->flags & CMIF_FLAG_PLAIN_SCHEDULE)))
+    return fail(CMIF_ERR_UNSUPPORTED,
+                "displacement windows are HARD mode, fused schedule only");
   if (d->n_angles < 1)
     return fail(CMIF_ERR_INVALID_ARGUMENT, "n_angles must be >= 1");
   if (d->angles_rad == nullptr && d->n_angles != 1)
@@ -1306,6 +1315,7 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   P->d = *d;
   P->d.h_a = P->d.w_a = P->d.h_b = P->d.w_b = nullptr;
   P->d.angles_rad = nullptr;
+  P->d.window = nullptr;
   if (d->tune_cache_path) P->tune_path = d->tune_cache_path;
   P->d.tune_cache_path = nullptr;
   for (int p = 0; p < d->n_pairs; ++p) {
@@ -1316,10 +1326,25 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
       delete P;
       return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be in [1, 1024]");
     }
-    g.sh = g.ha + g.hb - 1;
-    g.sw = g.wa + g.wb - 1;
-    g.ph = pow2_at_least(g.sh);
-    g.pw = pow2_at_least(g.sw);
+    // displacement window (default: the full set) and its alias-free FFT
+    // sides: lag chi and chi +- P must not both lie in the full set
+    int y0 = 1 - g.ha, y1 = g.hb - 1, x0 = 1 - g.wa, x1 = g.wb - 1;
+    if (d->window) {
+      const int32_t* w = d->window + 4 * p;
+      if (w[0] < y0 || w[1] > y1 || w[0] > w[1] || w[2] < x0 || w[3] > x1 ||
+          w[2] > w[3]) {
+        delete P;
+        return fail(CMIF_ERR_INVALID_ARGUMENT,
+                    "window of pair " + std::to_string(p) +
+                        " is empty or outside the displacement set");
+      }
+      y0 = w[0]; y1 = w[1]; x0 = w[2]; x1 = w[3];
+    }
+    g.eha = 1 - y0; g.ehb = y1 + 1; g.ewa = 1 - x0; g.ewb = x1 + 1;
+    g.sh = y1 - y0 + 1;
+    g.sw = x1 - x0 + 1;
+    g.ph = pow2_at_least(std::max(y1 + g.ha, g.hb - y0));
+    g.pw = pow2_at_least(std::max(x1 + g.wa, g.wb - x0));
     if (g.ph > kMaxP || g.pw > kMaxP) {
       delete P;
       return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 2048");

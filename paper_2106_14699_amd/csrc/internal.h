@@ -73,18 +73,16 @@ __host__ __device__ constexpr int stage_swz(int row) {
   return TW == 8 ? ((row >> 1) & 3) << 1 : (row >> 1) & (TW - 1);
 }
 
-// Map row of a circular correlation row y (P_h periodic): chi_y = y for
-// y <= h_b - 1, chi_y = y - P_h for y >= P_h - h_a + 1; -1 if unused.
-__host__ __device__ inline int circ_to_map(int y, int p, int h_a, int h_b) {
-  if (y <= h_b - 1) return y + h_a - 1;
-  if (y >= p - h_a + 1) return y - p + h_a - 1;
-  return -1;
-}
-
-// Inverse of circ_to_map: circular index of map row i.
-__host__ __device__ inline int map_to_circ(int i, int p, int h_a) {
-  int chi = i - (h_a - 1);
-  return chi >= 0 ? chi : chi + p;
+// Map row (or column) of circular correlation lag y (P periodic) in a
+// displacement window chi in [1 - e_a, e_b - 1]; -1 if lag y carries no
+// displacement of the window.  e_a, e_b are the window's extents on either
+// side of zero: the image sides h_a, h_b for the full set, 1 - y0 and
+// y1 + 1 for a window [y0, y1] (either may be <= 0 when the window does not
+// contain 0).  With P alias-free for the window, lag y holds chi = y for
+// y <= e_b - 1 and chi = y - P otherwise.
+__host__ __device__ inline int circ_to_map(int y, int p, int e_a, int e_b) {
+  const int chi = y <= e_b - 1 ? y : y - p;
+  return chi >= 1 - e_a && chi <= e_b - 1 ? chi + e_a - 1 : -1;
 }
 
 }  // namespace cmif

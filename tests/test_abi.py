@@ -268,7 +268,8 @@ def test_autotune_plan_and_cache_file(cm, tmp_path):
     assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
         == (2, 0, 0)
     ph, pw = info["fft_h"], info["fft_w"]
-    key = f"cmif-tune v1 gfx950 {ph}x{pw} qa=4 qb=4 prec=0 batch={info['angle_batch']}"
+    key = (f"cmif-tune v1 gfx950 {ph}x{pw}:127x127 qa=4 qb=4 prec=0 "
+           f"batch={info['angle_batch']}")
     f = tmp_path / "tune.txt"
     # a missing file, then malformed or out-of-range lines, are ignored
     assert _tune_plan(cm, str(f))["tuned"] == 0
@@ -285,6 +286,49 @@ def test_autotune_plan_and_cache_file(cm, tmp_path):
     # without the flag, or for SOFT, the file is not consulted
     assert _tune_plan(cm, str(f), flags=0)["tuned"] == 0
     assert _tune_plan(cm, str(f), mode=cm.CMIF_MODE_SOFT)["tuned"] == 0
+
+
+def _window_desc(cm, sizes, windows, **kw):
+    d = make_desc(cm, sizes=sizes, **kw)
+    if windows is not None:
+        arr = (ctypes.c_int32 * (4 * len(windows)))(*[v for w in windows for v in w])
+        d.window = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+        d._keep = (d._keep, arr)
+    return d
+
+
+def _fft_sides(cm, d):
+    h = cm.cmif_plan(d)
+    try:
+        info = cm.cmif_plan_query(h)
+        return (info["fft_h"], info["fft_w"]), cm.cmif_workspace_size(h)[1]
+    finally:
+        cm.cmif_plan_free(h)
+
+
+def test_window_validation_and_fft_sides(cm):
+    s = ((400, 400, 400, 400),)
+    # full set: 799 -> 1024; +-100 needs max(100 + 400, 400 + 100) -> 512
+    full, scr_full = _fft_sides(cm, _window_desc(cm, s, None))
+    assert full == (1024, 1024)
+    win, scr_win = _fft_sides(cm, _window_desc(cm, s, [(-100, 100, -100, 100)]))
+    assert win == (512, 512) and scr_win < scr_full
+    # one displacement at 0 needs only max(h_a, h_b)
+    assert _fft_sides(cm, _window_desc(cm, s, [(0, 0, 0, 0)]))[0] == (512, 512)
+    # a window on one side only: max(300 + 400, 400 - 10) -> 1024 rows
+    assert _fft_sides(cm, _window_desc(cm, s, [(10, 300, -5, 5)]))[0] == (1024, 512)
+    # the full set written out is the same plan as NULL
+    assert _fft_sides(cm, _window_desc(cm, s, [(-399, 399, -399, 399)]))[0] == full
+    for bad in [(5, 4, 0, 0), (0, 0, 3, 2), (-400, 0, 0, 0), (0, 400, 0, 0),
+                (0, 0, -400, 0), (0, 0, 0, 400)]:
+        assert plan_status(cm, _window_desc(cm, s, [bad])) == cm.CMIF_ERR_INVALID_ARGUMENT, bad
+    # SOFT and the plain schedule take the full set only
+    d = _window_desc(cm, ((64, 64, 64, 64),), [(-3, 3, -3, 3)])
+    d.mode = cm.CMIF_MODE_SOFT
+    assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
+    d = _window_desc(cm, ((64, 64, 64, 64),), [(-3, 3, -3, 3)])
+    d.precision, d.flags = cm.CMIF_PREC_FP64, cm.CMIF_FLAG_PLAIN_SCHEDULE
+    assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
 
 
 def test_status_strings(cm):
