@@ -14,6 +14,7 @@ no CPU or PyTorch fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Sequence
 
@@ -496,6 +497,42 @@ class Plan:
                                  for k in range(na)]
                                 for p in range(len(self.sizes))]
         return res
+
+
+def align_two_stage(A, MA, B, MB, size, q_a, q_b, grid, *, n_refine=32,
+                    rng=None, refine_angles=None, gamma=0.5, precision="fp32",
+                    flags=0, window=None, device=0):
+    """Global rigid alignment run twice (Sec. 3.6): Alg. 1 over the grid of
+    angles `grid`, then over n_refine angles drawn uniformly from
+    [theta* - 2 pi/|grid|, theta* + 2 pi/|grid|] around the grid's best
+    angle theta*.  A refinement result replaces the grid's only with a
+    strictly larger MI (the refinement angles come after the grid in Alg. 1's
+    order).  One image pair of sides `size` = (h_a, w_a, h_b, w_b).  The
+    draws come from `rng` (a numpy Generator), or the caller passes the
+    refinement angles themselves.  Both stages run through cmif_align.
+    Returns dict(best, stage ('grid' or 'refine'), grid_best, refine_best,
+    refine_angles)."""
+    import numpy as np
+    grid = [float(t) for t in grid]
+    wins = None if window is None else [tuple(window)]
+    p1 = Plan([size], q_a, q_b, angles=grid, gamma=gamma, precision=precision,
+              flags=flags, device=device, windows=wins)
+    g = p1.align(A, MA, B, MB)["best"][0]
+    del p1
+    if refine_angles is None:
+        if rng is None:
+            raise ValueError("pass rng (numpy Generator) or refine_angles")
+        half = 2.0 * math.pi / len(grid)
+        refine_angles = rng.uniform(g["angle_rad"] - half, g["angle_rad"] + half,
+                                    int(n_refine))
+    refine_angles = [float(t) for t in np.asarray(refine_angles).ravel()]
+    p2 = Plan([size], q_a, q_b, angles=refine_angles, gamma=gamma,
+              precision=precision, flags=flags, device=device, windows=wins)
+    r = p2.align(A, MA, B, MB)["best"][0]
+    del p2
+    best, stage = (r, "refine") if r["mi"] > g["mi"] else (g, "grid")
+    return dict(best=best, stage=stage, grid_best=g, refine_best=r,
+                refine_angles=refine_angles)
 
 
 def _plan_backward(self, A, MA, B, MB, grad_mi, *, want_a=True, want_b=True):
