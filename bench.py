@@ -139,6 +139,51 @@ def soft_bench(cm, torch, np, synth, steps):
                      "(host syncs included)")
 
 
+def stress_bench(cm, torch, np, synth, dev, reps=3):
+    """1024x1024, Q 16, all-ones masks (joint counts up to 2^20), FFT 2048:
+    the FP32-rounded path with its residual check and FP64 re-run against
+    the full-FP64 path on the same GPU.  Median of `reps` computes each
+    (MI, N and digests emitted)."""
+    print("[bench] precision stress 1024x1024", file=sys.stderr, flush=True)
+    c = synth.config4()
+    n = 1024
+    ins = [dev(c[k]) for k in ("A", "MA", "B", "MB")]
+    out = {}
+    for prec in ("fp32", "fp64"):
+        plan = cm.Plan([(n, n, n, n)], c["qa"], c["qb"], angles=c["angles"],
+                       gamma=c["gamma"], precision=prec)
+        res = plan.compute(*ins, mi=True, n=True, digest=True, best=True)
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            res = plan.compute(*ins, mi=True, n=True, digest=True, best=True)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        out[prec] = dict(ms=float(np.median(times)), res=res,
+                         fft=plan.info()["fft_h"])
+        del plan
+    r32, r64 = out["fp32"]["res"], out["fp64"]["res"]
+    dmi = float((r32["mi"][0] - r64["mi"][0]).abs().max())
+    same_digests = bool(torch.equal(r32["digest"][0], r64["digest"][0]))
+    st = r32["stats"]
+    b32, b64 = r32["best"][0], r64["best"][0]
+    return dict(workload="1024x1024 uint8, Q_A=Q_B=16, all-ones masks, one "
+                         "angle, full 2047x2047 map",
+                fft=out["fp32"]["fft"],
+                fp32_rounded_ms=round(out["fp32"]["ms"], 3),
+                fp64_ms=round(out["fp64"]["ms"], 3),
+                speedup=round(out["fp64"]["ms"] / out["fp32"]["ms"], 3),
+                max_residual=st["max_residual"],
+                flagged_pairs=st["flagged_pairs"],
+                fallback_pairs=st["fallback_pairs"],
+                max_abs_dmi_vs_fp64=dmi, digests_equal=same_digests,
+                same_best=(b32["dy"], b32["dx"]) == (b64["dy"], b64["dx"]),
+                planted_shift=list(c["shift"]), best=[b32["dy"], b32["dx"]])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +197,8 @@ def main():
     ap.add_argument("--no-soft", action="store_true",
                     help="skip the soft-membership batch")
     ap.add_argument("--soft-steps", type=int, default=5)
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the 1024x1024 precision-stress comparison")
     ap.add_argument("--no-window", action="store_true",
                     help="skip the windowed sweep (Alg. 1's padded window)")
     ap.add_argument("--copy-gib", type=float, default=0.0)
@@ -298,6 +345,10 @@ def main():
                       (best["angle_index"], best["dy"], best["dx"]))
         del wplan
 
+    stress = None
+    if not args.no_stress:
+        stress = stress_bench(cm, torch, np, synth, dev)
+
     soft = None
     if not args.no_soft:
         print("[bench] soft batch", file=sys.stderr, flush=True)
@@ -353,6 +404,7 @@ def main():
                                         float(np.median(step_ms)), 3)
                                   if plain else None),
         "window_sweep": window,
+        "precision_stress": stress,
         "soft": soft,
         "launch_shapes": {k: info1[k] for k in ("rows_per_wg", "labels_per_team",
                                                 "xcd_grouping", "tuned",
