@@ -145,9 +145,10 @@ struct cmif_plan_s {
   int graph_captures = 0;
   int graph_replays = 0;
   // launch shapes (defaults, or the autotuner's choice)
-  int rows_per_wg = 2;   // pair row kernel: map rows per workgroup
+  int rows_per_wg = 1;   // pair row kernel: map rows per workgroup
   int bpw = 0;           // pair row kernel: labels of B per team (0: default)
   int xcd = 0;           // pair column kernel: XCD-grouped order
+  int def_xcd = 0;       // the default order (set by cmif_plan)
   int tuned = 0;         // 0 default, 1 timed, 2 read from the cache
   int tune_runs = 0;
   std::string tune_path;
@@ -853,7 +854,7 @@ cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
     for (int rpw : {1, 2, 4}) cands.push_back({rpw, bpw, (int)(cands.size() & 1)});
   }
   double best_rows = 1e300, best_cols[2] = {1e300, 1e300};
-  Cand pick{2, 0, 0};
+  Cand pick{1, 0, P->def_xcd};
   // an untimed pass first: code loading and cold caches stay out of the choice
   cmif_status s = pass(st);
   if (s == CMIF_OK) {
@@ -882,9 +883,9 @@ cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
   P->prof.recs.swap(saved);
   P->prof.used = used0;
   if (s != CMIF_OK) {
-    P->rows_per_wg = 2;
+    P->rows_per_wg = 1;
     P->bpw = 0;
-    P->xcd = 0;
+    P->xcd = P->def_xcd;
     return s;
   }
   P->rows_per_wg = pick.rpw;
@@ -1417,6 +1418,11 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   size_t smax = 0;
   for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);
   P->scratch_bytes = smax;
+  // default column order: XCD-grouped where its F_B re-reads cost time (FP64
+  // spectra, 2048-point columns; measured 7-12 % faster there), launch
+  // order otherwise (at FP32 P <= 1024 it was 1-3 % faster)
+  P->def_xcd = (d->precision == CMIF_PREC_FP64 || P->pairs[0].ph >= 2048) ? 1 : 0;
+  P->xcd = P->def_xcd;
   if (tunable(P)) {
     P->tune_key = tune_key(P);
     if (!P->tune_path.empty() && tune_read(P)) P->tuned = 2;

@@ -282,13 +282,18 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   }
 }
 
+// Lanes of the count kernel's workgroup: up to four teams, at most 512 lanes
+// (two waves per SIMD keep 256 registers per lane; at 1024 lanes the
+// 2048-point kernel spilled; team_for gives at most 256 lanes, a divisor of 512).
+constexpr int counts_lanes(int team) { return 4 * team <= 512 ? 4 * team : 512; }
+
 // Count emission: workgroup (map row, angle); each team takes label pairs
 // two at a time (a-major order) and writes rint(count) to
 // counts[beta][pair][i][j] and/or adds sum_j count * splitmix64(i*S_w + j)
 // into digest[beta][pair] (64-bit wrap-around, order-free).  In item mode
 // the slots of Z are list items (angle, a, b) and the grid has one angle.
 template <typename T, int P, int TEAM>
-__global__ void __launch_bounds__(4 * TEAM)
+__global__ void __launch_bounds__(counts_lanes(TEAM))
 k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
               long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
               int sw, int ph, const C2<T>* __restrict__ tw,
@@ -438,7 +443,7 @@ template <typename T, int P>
 hipError_t launch_pair_counts_p(const PairCountsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = team_for(P);
   const size_t per_team = (size_t)lds_elems(P) * sizeof(C2<T>);
-  int nteams = 4;
+  int nteams = counts_lanes(TEAM) / TEAM;
   while (nteams > 1 && per_team * nteams > 64 * 1024) --nteams;
   const size_t shm = per_team * nteams;
   auto fn = k_pair_counts<T, P, TEAM>;

@@ -198,22 +198,38 @@ inline size_t pair_rows_lds(size_t elem_real, int P, int nteams) {
          (split ? (size_t)nteams * 2 * P * 2 * elem_real : 0);
 }
 
-// false when no supported shape fits (LDS above 160 KiB or > 1024 lanes)
+// Default shape (the launch-shape tuner may pick another).  The labels per
+// team set the per-lane state (BPW counters per point) and, through the
+// team count, the launch bound and so the register budget per lane; the
+// default takes the smallest bpw whose workgroup stays within a lane cap:
+// FP32 512 lanes (two waves per SIMD, 256 registers), FP64 128 lanes (its
+// state needs the 512 registers of one wave per SIMD; more teams spill).
+// Without such a bpw, the one with the fewest lanes.  Measured: FP32 at
+// P = 2048 with 8 labels per team 3.4x faster than with 4 (1024 lanes,
+// 128 registers, 368 bytes of spills); FP64 at P = 1024 and 2048 with 16
+// 2.4x faster than with 4.  false when no supported shape fits (LDS above
+// 160 KiB or > 1024 lanes).
 inline bool pair_rows_config(size_t elem_real, int P, int QB, PairRowsConfig* c) {
   const int team = team_for(P);
+  const int cap = elem_real == sizeof(float) ? 512 : 128;
+  bool found = false;
   for (int bpw : {4, 8, 16}) {
     const int nteams = (QB + bpw - 1) / bpw;
     const int nt = nteams * team;
     if (nt > 1024) continue;
     const size_t lds = pair_rows_lds(elem_real, P, nteams);
     if (lds > 160 * 1024) continue;
+    // keep the first fit, replace it while it is above the cap
+    if (found && c->nteams * team <= cap) break;
+    if (found && nteams >= c->nteams) continue;
     c->bpw = bpw;
     c->nteams = nteams;
     c->ntmax = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
     c->lds = lds;
-    return true;
+    found = true;
+    if (nt <= cap) break;
   }
-  return false;
+  return found;
 }
 
 // The shape for a given bpw (4, 8 or 16); false if it does not fit.

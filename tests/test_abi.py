@@ -266,7 +266,7 @@ def test_autotune_plan_and_cache_file(cm, tmp_path):
     info = _tune_plan(cm, None)
     assert (info["tuned"], info["tune_runs"]) == (0, 0)
     assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
-        == (2, 0, 0)
+        == (1, 0, 0)
     ph, pw = info["fft_h"], info["fft_w"]
     key = (f"cmif-tune v1 gfx950 {ph}x{pw}:127x127 qa=4 qb=4 prec=0 "
            f"batch={info['angle_batch']}")
