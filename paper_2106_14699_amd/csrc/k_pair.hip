@@ -15,16 +15,29 @@
 
 namespace cmif {
 
+// Columns per workgroup (one team each): the whole TW-wide tile, or part of
+// it where TW teams would exceed 512 lanes (FP32) or 256 lanes (FP64) — at
+// 1024 lanes the launch bound leaves 128 registers per lane and the
+// 2048-point kernel spilled.  A part writes its columns of every 64-byte
+// row segment as 32-byte pieces.
+template <typename T, int P>
+constexpr int pair_cols_cpw() {
+  constexpr int cap = sizeof(T) == 4 ? 512 : 256;
+  constexpr int team = pair_col_team<T>(P);
+  return tile_width<T>() * team <= cap ? tile_width<T>()
+                                       : (cap / team >= 2 ? cap / team : 2);
+}
+
 // LDS of the column kernel: the teams' exchange buffers (re-used as the
 // staging tile) and, when it fits, the twiddle table (otherwise every lane
 // keeps its twiddles in registers).
 template <typename T, int P>
 constexpr size_t pair_cols_exch_bytes() {
-  return (size_t)tile_width<T>() * lds_elems(P) * sizeof(C2<T>);
+  return (size_t)pair_cols_cpw<T, P>() * lds_elems(P) * sizeof(C2<T>);
 }
 template <typename T, int P>
 constexpr size_t pair_cols_stage_bytes() {
-  return (size_t)P * tile_width<T>() * sizeof(C2<T>);
+  return (size_t)P * pair_cols_cpw<T, P>() * sizeof(C2<T>);
 }
 // A staging tile of its own (instead of the exchange buffers) when it fits:
 // one barrier less per label b, and the copy-out of b overlaps the next FFT.
@@ -43,15 +56,24 @@ constexpr bool pair_cols_lds_twiddles() {
   return pair_cols_table_offset<T, P>() + (size_t)P * sizeof(C2<T>) <= 160 * 1024;
 }
 
-// Staging + store of one b's TW columns: rows i of the tile leave as 16-byte
-// vectors into Z[a*Q_B+b][tile][i][TW].
+// Column swizzle of the [rows][CPW] staging tile: a multiple of the 16-byte
+// vector's EV elements (vectors of a row stay whole), varying with the row
+// so that one column written for consecutive rows spreads over the banks.
+template <int CPW, int EV>
+__device__ __forceinline__ int pc_swz(int row) {
+  return ((row >> 1) & (CPW / EV - 1)) * EV;
+}
+
+// Staging + store of one b's CPW columns (columns part*CPW .. of the tile):
+// rows i leave as 16-byte vectors into Z[a*Q_B+b][tile][i][TW].
 template <typename T, int P, int TEAM>
 __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* smem,
                                                 C2<T>* __restrict__ zp, int ha,
                                                 int hb, int sh, int team,
-                                                int lane) {
+                                                int part, int lane) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
+  constexpr int CPW = pair_cols_cpw<T, P>();
   constexpr int EV = 16 / (int)sizeof(C2<T>);
   constexpr bool SEP = pair_cols_sep_staging<T, P>();
   C2<T>* stage = SEP ? reinterpret_cast<C2<T>*>(reinterpret_cast<unsigned char*>(smem) +
@@ -63,13 +85,14 @@ __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* sme
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = circ_to_map(lane + TEAM * q, P, ha, hb);
-    if (i >= 0) stage[i * TW + (team ^ stage_swz<TW>(i))] = v[q];
+    if (i >= 0) stage[i * CPW + (team ^ pc_swz<CPW, EV>(i))] = v[q];
   }
   __syncthreads();
   float4* z4 = reinterpret_cast<float4*>(zp);
-  for (int e = threadIdx.x; e < sh * TW / EV; e += blockDim.x) {
-    const int i = (e * EV) / TW, col = (e * EV) % TW;
-    z4[e] = *reinterpret_cast<const float4*>(&stage[i * TW + (col ^ stage_swz<TW>(i))]);
+  for (int e = threadIdx.x; e < sh * CPW / EV; e += blockDim.x) {
+    const int i = (e * EV) / CPW, col = (e * EV) % CPW;
+    z4[(i * TW + part * CPW + col) / EV] =
+        *reinterpret_cast<const float4*>(&stage[i * CPW + (col ^ pc_swz<CPW, EV>(i))]);
   }
   if constexpr (!SEP) __syncthreads();  // the exchange buffers are reused next
 }
@@ -81,7 +104,7 @@ __device__ __forceinline__ void pair_cols_run(
     const C2<T>* __restrict__ fa_col, const C2<T>* __restrict__ fb_base,
     long long fb_label_stride, int b_begin, int b_end, int zpair0, int ha,
     int hb, int sh, C2<T>* __restrict__ z_base, long long z_pair_stride,
-    const TWS& ftw, C2<T>* smem, int c, int team, int lane) {
+    const TWS& ftw, C2<T>* smem, int c, int team, int part, int lane) {
   constexpr int R = P / TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
   if (fa_col == nullptr) {
@@ -94,7 +117,7 @@ __device__ __forceinline__ void pair_cols_run(
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM>(
           v, smem, z_base + (long long)(zpair0 + b - b_begin) * z_pair_stride, ha,
-          hb, sh, team, lane);
+          hb, sh, team, part, lane);
     }
     return;
   }
@@ -121,7 +144,7 @@ __device__ __forceinline__ void pair_cols_run(
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM>(
           v, smem, z_base + (long long)(zpair0 + b - b_begin) * z_pair_stride, ha,
-          hb, sh, team, lane);
+          hb, sh, team, part, lane);
     }
   } else {
     // slot 0 packs the k_x = 0 and k_x = P_w/2 columns (both Hermitian)
@@ -142,13 +165,13 @@ __device__ __forceinline__ void pair_cols_run(
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM>(
           v, smem, z_base + (long long)(zpair0 + b - b_begin) * z_pair_stride, ha,
-          hb, sh, team, lane);
+          hb, sh, team, part, lane);
     }
   }
 }
 
 template <typename T, int P, int TEAM>
-__global__ void __launch_bounds__(tile_width<T>() * TEAM)
+__global__ void __launch_bounds__((pair_cols_cpw<T, P>() * TEAM))
 k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
             const C2<T>* __restrict__ FB, long long fb_angle_stride,
             long long fb_label_stride, int QB, int ha, int hb, int sh,
@@ -159,7 +182,8 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int TW = tile_width<T>();
-  int t = blockIdx.x;
+  constexpr int NPART = TW / pair_cols_cpw<T, P>();  // workgroups per tile
+  int t = blockIdx.x;  // tile part: tile t / NPART, part t % NPART
   int a, beta, b_begin, b_end, zpair0;
   C2<T>* z_base;
   if (items == nullptr) {
@@ -180,7 +204,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     b_begin = 0;
     b_end = QB;
     zpair0 = a * QB;
-    z_base = Z + beta * z_angle_stride + (long long)t * sh * TW;
+    z_base = Z + beta * z_angle_stride + (long long)(t / NPART) * sh * TW;
   } else {
     // item list: workgroup (tile, item) runs one pair (angle, a, b) of the
     // list into slot `item` of Z
@@ -192,11 +216,12 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     b_begin = e.z;
     b_end = e.z + 1;
     zpair0 = it;
-    z_base = Z + (long long)t * sh * TW;
+    z_base = Z + (long long)(t / NPART) * sh * TW;
   }
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
-  const int c = t * TW + team;
+  const int part = t % NPART;
+  const int c = (t / NPART) * TW + part * pair_cols_cpw<T, P>() + team;
   const C2<T>* fa_col = FA ? FA + a * fa_label_stride + (long long)c * P : nullptr;
   const C2<T>* fb_base = FB + beta * fb_angle_stride + (long long)c * P;
   if constexpr (pair_cols_lds_twiddles<T, P>()) {
@@ -207,20 +232,21 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     const FftTwTable<T, P, TEAM> ftw{twl};
     pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, b_begin, b_end,
                               zpair0, ha, hb, sh, z_base, z_pair_stride, ftw,
-                              smem, c, team, lane);
+                              smem, c, team, part, lane);
   } else {
     FftTw<T, P, TEAM> ftw;
     fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
     pair_cols_run<T, P, TEAM>(fa_col, fb_base, fb_label_stride, b_begin, b_end,
                               zpair0, ha, hb, sh, z_base, z_pair_stride, ftw,
-                              smem, c, team, lane);
+                              smem, c, team, part, lane);
   }
 }
 
 template <typename T, int P>
 static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = pair_col_team<T>(P);
-  constexpr int TW = tile_width<T>();
+  constexpr int CPW = pair_cols_cpw<T, P>();
+  constexpr int NPART = tile_width<T>() / CPW;
   const size_t shm = pair_cols_table_offset<T, P>() +
                      (pair_cols_lds_twiddles<T, P>() ? (size_t)P * sizeof(C2<T>) : 0);
   auto fn = k_pair_cols<T, P, TEAM>;
@@ -228,10 +254,11 @@ static hipError_t launch_pc_p(const PairColsArgs<T>& a, hipStream_t st) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
   if (e != hipSuccess) return e;
-  dim3 grid = a.items ? dim3(a.tiles, a.max_items, 1) : dim3(a.tiles, a.QA, a.nb);
+  const int parts = a.tiles * NPART;
+  dim3 grid = a.items ? dim3(parts, a.max_items, 1) : dim3(parts, a.QA, a.nb);
   const int xcd_groups =
-      !a.items && a.xcd != 0 && ((long long)a.tiles * a.nb) % 8 == 0;
-  hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.FA, a.fa_label_stride,
+      !a.items && a.xcd != 0 && ((long long)parts * a.nb) % 8 == 0;
+  hipLaunchKernelGGL(fn, grid, dim3(CPW * TEAM), shm, st, a.FA, a.fa_label_stride,
                      a.FB, a.fb_angle_stride, a.fb_label_stride, a.QB, a.ha,
                      a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw,
                      a.items, a.n_items, xcd_groups);
