@@ -42,9 +42,10 @@ def _digest(oracle, counts):
 # (ha, wa, hb, wb) per pair and a window per pair: containing 0, all
 # positive, all negative, one displacement, one row
 SIZES = [(41, 47, 36, 52), (33, 40, 45, 38), (30, 44, 30, 44), (25, 31, 28, 27),
-         (38, 35, 33, 29)]
+         (38, 35, 33, 29), (150, 140, 160, 150)]
 WINDOWS = [(-12, 9, -20, 14), (3, 30, 5, 37), (-29, -6, -30, -2), (4, 4, -7, -7),
-           (-5, -5, -34, 28)]
+           (-5, -5, -34, 28), (-30, 30, -20, 25)]
+# the last pair: FFT 256 x 256 with its window, 512 x 512 for the full set
 
 
 @pytest.mark.parametrize("precision,flags", [("fp32", 0), ("fp64", 0),
@@ -65,6 +66,9 @@ def test_windows_match_oracle_and_full_maps(gpu, oracle, precision, flags):
                     per_angle=True)
     rf = pf.compute(*ins, mi=True, n=True)
     near = 0
+    last = len(SIZES) - 1
+    assert cm.cmif_plan_query(pw.handle)["fft_h"] == 128  # pair 0
+    assert pw.map_shape(last) == (61, 46)
     for p, (s, w, c) in enumerate(zip(SIZES, WINDOWS, cases)):
         ha, wa, hb, wb = s
         assert tuple(rw["mi"][p].shape[1:]) == (w[1] - w[0] + 1, w[3] - w[2] + 1)
