@@ -146,6 +146,17 @@ def config3(n_angles: int = 180, size: int = 512, q: int = 16):
                 angles=angles, gamma=0.5, shift=s, theta_deg=theta)
 
 
+def table1_pair(n: int, q: int = 16):
+    """An n x n pair shaped like the paper's alignment benchmark images
+    (cytological 300 x 300, histological 834 x 834): the config-3 generator
+    (blur sigma 4, rotation in [0, 360) deg, shift within n/10, noise 0.2,
+    relabelled B) at side n; M_A all ones, M_B the rotation footprint."""
+    rng = np.random.default_rng(seed_for(6, n))
+    a, b, mb, s, theta = rotated_pair(rng, 4.0, n, q, n // 2, n // 10, 0.2)
+    return dict(name=f"table1-{n}x{n}-q{q}", A=a, MA=np.ones((n, n), np.uint8),
+                B=b, MB=mb, qa=q, qb=q, shift=s, theta_deg=theta)
+
+
 def config4():
     """1024x1024, Q=16, blur sigma 6, B = quantised cos(2.5 f) + 0.2 N(0,1)
     moved by a seeded shift in [-8, 8]^2; all-ones masks (overlap counts up
