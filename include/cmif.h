@@ -349,6 +349,35 @@ typedef struct cmif_plan_info {
 /* Fills *info (host memory).  Errors: CMIF_ERR_INVALID_ARGUMENT on NULL. */
 cmif_status cmif_plan_query(cmif_plan_t plan, cmif_plan_info* info);
 
+/* Mini-batch k-means quantisation of an image into k labels: the QUANTIZE
+   step of Alg. 1 (Sec. 3.6), with the mini-batch algorithm of Sculley
+   (2010) that the paper uses.  Pixels are rows of `channels` FP32 values
+   (device image[n_pixels][channels]); arithmetic is FP64.  Initial centres:
+   the pixels init_idx[k] (device int32; Sculley's random examples), or,
+   with init_idx NULL, the values already in `centers`.  Iteration t takes
+   the batch batches[t][0..batch) (device int32 pixel indices, drawn by the
+   caller), assigns each to its nearest centre under the centres at the
+   start of the iteration, then applies the samples in batch order: the
+   centre's count v increases by one and the centre moves to
+   (1 - 1/v) c + (1/v) x, so every centre is the running mean of the
+   samples assigned to it (no random reassignment of small clusters).
+   Then every pixel gets the index of its nearest centre (squared
+   Euclidean distance summed over channels in order, ties to the lowest
+   index) in labels[n_pixels] (device uint8), 0 where mask (device uint8,
+   NULL = all ones) is 0.  centers: device double[k][channels], in (without
+   init_idx) and out.  bad_indices: device uint32 or NULL; each init or
+   batch index outside [0, n_pixels) adds 1 there and is otherwise skipped
+   (an initial centre from one is 0).  Enqueued on `stream` on the current
+   device.  Errors: CMIF_ERR_INVALID_ARGUMENT (NULL image/centers/labels,
+   batches NULL with iters > 0, n_pixels < 1, k outside 1..64, channels
+   outside 1..8, batch outside 1..8192 with iters > 0, iters outside
+   0..100000), CMIF_ERR_NO_DEVICE, CMIF_ERR_DEVICE. */
+cmif_status cmif_kmeans(const float* image, const uint8_t* mask,
+                        int64_t n_pixels, int32_t channels, int32_t k,
+                        const int32_t* init_idx, const int32_t* batches,
+                        int32_t iters, int32_t batch, double* centers,
+                        uint8_t* labels, uint32_t* bad_indices, void* stream);
+
 /* Static description of a status code. */
 const char* cmif_status_string(cmif_status status);
 

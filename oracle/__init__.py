@@ -13,8 +13,13 @@ Two parts:
     Eq. 12 entropies, differentiated by autograd.  It is pinned against the C
     direct method and against central finite differences in the tests.
 
+  * kmeans_* below, plain numpy in FP64: the mini-batch k-means quantiser
+    (the QUANTIZE step of Alg. 1, Sec. 3.6; Sculley 2010) written as its
+    per-sample steps.
+
 Every function states the passage it follows.  All parts are pinned by
-tests/test_oracle_pins.py; none is "parity unpinned".
+tests/test_oracle_pins.py and tests/test_kmeans_oracle.py; none is "parity
+unpinned".
 """
 
 from __future__ import annotations
@@ -298,3 +303,68 @@ def soft_loss_torch(pairs, gamma=0.5, temperature=0.01):
         maps.append(mi)
         elig.append(e)
     return total, maps, elig
+
+
+# ---------------------------------------------------------------------------
+# Mini-batch k-means (the QUANTIZE step of Alg. 1, Sec. 3.6).
+# ---------------------------------------------------------------------------
+
+def _as_pixels(img):
+    x = np.asarray(img)
+    return x.reshape(x.shape[0] * x.shape[1], -1) if x.ndim == 3 else x.reshape(-1, 1)
+
+
+def kmeans_nearest(x, centers):
+    """Index of the nearest centre for each row of x (FP64 squared
+    Euclidean distance, channels accumulated in order; ties to the lowest
+    index, as np.argmin returns the first minimum)."""
+    x = np.asarray(x, np.float64)
+    c = np.asarray(centers, np.float64)
+    d = np.zeros((x.shape[0], c.shape[0]), np.float64)
+    for ch in range(x.shape[1]):
+        e = x[:, ch][:, None] - c[:, ch][None, :]
+        d = d + e * e
+    return np.argmin(d, axis=1)
+
+
+def kmeans_minibatch(img, k, init_idx=None, batches=None, centers=None):
+    """Sculley's mini-batch k-means, the quantiser the paper uses (Sec. 3.6):
+    centres start at the pixels init_idx (or at `centers`); per batch, every
+    sample is assigned to its nearest centre under the centres at the start
+    of the batch, then the samples are applied in batch order: the centre's
+    count v grows by one and the centre becomes (1 - 1/v) c + (1/v) x.
+    Indices outside the image are skipped.  Pixels are rows of channels
+    (img [H, W] or [H, W, m], or already [n, m]).  Returns the centres
+    [k, m] (FP64)."""
+    x = _as_pixels(img)
+    n, m = x.shape
+    if centers is not None:
+        c = np.array(centers, np.float64).reshape(k, m)
+    else:
+        c = np.zeros((k, m), np.float64)
+        for j, idx in enumerate(np.asarray(init_idx).ravel()[:k]):
+            if 0 <= idx < n:
+                c[j] = x[idx].astype(np.float64)
+    v = np.zeros(k, np.int64)
+    for mb in ([] if batches is None else np.asarray(batches)):
+        mb = np.asarray(mb).ravel()
+        mb = mb[(mb >= 0) & (mb < n)]
+        pts = x[mb].astype(np.float64)
+        lab = kmeans_nearest(pts, c)
+        for p, j in zip(pts, lab):
+            v[j] += 1
+            eta = 1.0 / float(v[j])
+            c[j] = (1.0 - eta) * c[j] + eta * p
+    return c
+
+
+def kmeans_labels(img, centers, mask=None):
+    """Nearest-centre label of every pixel, 0 outside the mask (uint8,
+    image shape)."""
+    x = _as_pixels(img)
+    lab = kmeans_nearest(x, centers).astype(np.uint8)
+    if mask is not None:
+        lab[np.asarray(mask).reshape(-1) == 0] = 0
+    shape = np.asarray(img).shape[:2]
+    return lab.reshape(shape)
+

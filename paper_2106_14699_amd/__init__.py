@@ -43,7 +43,7 @@ CMIF_FLAG_AUTOTUNE = 1 << 4
 EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_compute", "cmif_align", "cmif_backward",
             "cmif_profile_enable", "cmif_profile_read", "cmif_plan_query",
-            "cmif_status_string", "cmif_last_error")
+            "cmif_status_string", "cmif_last_error", "cmif_kmeans")
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
@@ -143,6 +143,10 @@ def _load_lib():
     lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
                                   _PP, _P, S, _P, S, _P]
     lib.cmif_backward.restype = ctypes.c_int
+    lib.cmif_kmeans.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                ctypes.c_int32, _P, _P, _P, _P]
+    lib.cmif_kmeans.restype = ctypes.c_int
     lib.cmif_plan_query.argtypes = [_P, ctypes.POINTER(cmif_plan_info)]
     lib.cmif_plan_query.restype = ctypes.c_int
     lib.cmif_profile_enable.argtypes = [_P, ctypes.c_int32]
@@ -497,6 +501,61 @@ class Plan:
                                  for k in range(na)]
                                 for p in range(len(self.sizes))]
         return res
+
+
+def cmif_kmeans(image, mask, n_pixels, channels, k, init_idx, batches, iters,
+                batch, centers, labels, bad_indices, stream) -> None:
+    _check(_lib.cmif_kmeans(_P(image), _P(mask), int(n_pixels), int(channels),
+                            int(k), _P(init_idx), _P(batches), int(iters),
+                            int(batch), _P(centers), _P(labels),
+                            _P(bad_indices), _P(stream)), "cmif_kmeans")
+
+
+def kmeans_quantize(image, k, *, iters=25, batch=1000, rng=None, mask=None,
+                    init_idx=None, batches=None):
+    """Quantise a device FP32 image ([H, W] or [H, W, m]) into k labels by
+    mini-batch k-means (cmif_kmeans).  The random draws are made here on the
+    host with `rng` (numpy Generator) unless given: k distinct in-mask
+    pixels seed the centres, and each of `iters` batches is `batch` in-mask
+    pixel indices drawn uniformly with replacement.  Returns dict(labels
+    uint8 [H, W], centers float64 [k, m], init_idx, batches, bad)."""
+    import numpy as np
+    import torch
+    if image.dtype != torch.float32 or not image.is_cuda:
+        raise ValueError("image must be a float32 device tensor")
+    img = image.contiguous()
+    h, w = img.shape[0], img.shape[1]
+    m = 1 if img.dim() == 2 else img.shape[2]
+    n = h * w
+    dev = img.device
+    msk = None
+    if mask is not None:
+        msk = mask.to(device=dev, dtype=torch.uint8).contiguous()
+    if init_idx is None or (batches is None and iters > 0):
+        if rng is None:
+            raise ValueError("pass rng or both init_idx and batches")
+        pool = (np.arange(n) if msk is None
+                else np.flatnonzero(msk.reshape(-1).cpu().numpy()))
+        if init_idx is None:
+            init_idx = rng.choice(pool, size=k, replace=False)
+        if batches is None and iters > 0:
+            batches = pool[rng.integers(0, pool.size, size=(iters, batch))]
+    init_t = torch.as_tensor(np.asarray(init_idx, np.int32), device=dev)
+    bt = (torch.as_tensor(np.asarray(batches, np.int32).reshape(iters, batch),
+                          device=dev) if iters > 0 else None)
+    centers = torch.zeros((k, m), dtype=torch.float64, device=dev)
+    labels = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    bad = torch.zeros((1,), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    cmif_kmeans(img.data_ptr(), msk.data_ptr() if msk is not None else None,
+                n, m, k, init_t.data_ptr(),
+                bt.data_ptr() if bt is not None else None, iters,
+                batch if iters > 0 else 1, centers.data_ptr(), labels.data_ptr(),
+                bad.data_ptr(), stream)
+    torch.cuda.current_stream(dev).synchronize()
+    return dict(labels=labels, centers=centers, init_idx=np.asarray(init_idx),
+                batches=None if batches is None else np.asarray(batches),
+                bad=int(bad.item()))
 
 
 def align_two_stage(A, MA, B, MB, size, q_a, q_b, grid, *, n_refine=32,

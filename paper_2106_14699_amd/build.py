@@ -26,7 +26,9 @@ SOURCES = [("api.cpp", "api", []), ("k_forward.hip", "k_forward", []),
            ("k_pair.hip", "k_pair", []), ("k_misc.hip", "k_misc", []),
            ("k_soft.hip", "k_soft_f32", ["-DCMIF_SOFT_T=float"]),
            ("k_soft.hip", "k_soft_f64", ["-DCMIF_SOFT_T=double"]),
-           ("k_rows.hip", "k_rows", [])]
+           ("k_rows.hip", "k_rows", []),
+           # plain FP64 evaluation order (no fused multiply-adds)
+           ("k_kmeans.hip", "k_kmeans", ["-ffp-contract=off"])]
 for _t, _tn in (("float", "f32"), ("double", "f64")):
     for _p in (128, 256, 512, 1024, 2048):
         SOURCES.append(("k_rows.hip", f"k_rows_{_tn}_{_p}",

@@ -1556,4 +1556,41 @@ cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
   return CMIF_OK;
 }
 
+cmif_status cmif_kmeans(const float* image, const uint8_t* mask,
+                        int64_t n_pixels, int32_t channels, int32_t k,
+                        const int32_t* init_idx, const int32_t* batches,
+                        int32_t iters, int32_t batch, double* centers,
+                        uint8_t* labels, uint32_t* bad_indices, void* stream) {
+  if (!image || !centers || !labels)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "image, centers and labels are required");
+  if (n_pixels < 1) return fail(CMIF_ERR_INVALID_ARGUMENT, "n_pixels must be >= 1");
+  if (k < 1 || k > 64) return fail(CMIF_ERR_INVALID_ARGUMENT, "k must be in [1, 64]");
+  if (channels < 1 || channels > 8)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "channels must be in [1, 8]");
+  if (iters < 0 || iters > 100000)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "iters must be in [0, 100000]");
+  if (iters > 0 && (!batches || batch < 1 || batch > 8192))
+    return fail(CMIF_ERR_INVALID_ARGUMENT,
+                "iters > 0 needs batches and batch in [1, 8192]");
+  int ndev = 0, dev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(CMIF_ERR_NO_DEVICE, "no HIP device");
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CMIF_ERR_DEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(CMIF_ERR_DEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(CMIF_ERR_NO_DEVICE,
+                std::string("libcmif is built for gfx950, device is ") + prop.gcnArchName);
+  KmeansArgs ka{};
+  ka.img = image; ka.mask = mask; ka.n = n_pixels; ka.m = channels; ka.k = k;
+  ka.init_idx = init_idx; ka.batches = iters > 0 ? batches : nullptr;
+  ka.iters = iters; ka.batch = iters > 0 ? batch : 1;
+  ka.centers = centers; ka.labels = labels; ka.bad = bad_indices;
+  const hipError_t e = launch_kmeans(ka, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(CMIF_ERR_DEVICE, std::string("k-means launch: ") + hipGetErrorString(e));
+  return CMIF_OK;
+}
+
 }  // extern "C"

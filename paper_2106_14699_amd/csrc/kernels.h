@@ -320,4 +320,19 @@ struct PlainEntropyArgs {
 hipError_t launch_plain_entropy(const PlainEntropyArgs& a, hipStream_t st);
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
 
+// Mini-batch k-means quantisation (k_kmeans.hip).
+struct KmeansArgs {
+  const float* img;         // [n][m] pixels x channels
+  const uint8_t* mask;      // [n] or nullptr (labels 0 outside)
+  int64_t n;
+  int m, k;
+  const int32_t* init_idx;  // [k] pixels that seed the centres, or nullptr
+  const int32_t* batches;   // [iters][batch] pixel indices
+  int iters, batch;
+  double* centers;          // [k][m] in (without init_idx) / out
+  uint8_t* labels;          // [n]
+  uint32_t* bad;            // out-of-range indices seen (may be nullptr)
+};
+hipError_t launch_kmeans(const KmeansArgs& a, hipStream_t st);
+
 }  // namespace cmif

@@ -97,20 +97,18 @@ def config2():
                 gamma=0.5, shift=s)
 
 
-def rotated_pair(rng, sigma, n, q, margin, shift_range, noise_sd):
-    """B(p) = perm(qq(cos(2.5 F(src(p))) + noise)) with
-    src(p) = R(-theta)(p - c) + c - s, evaluated in FP64 and rounded to the
-    nearest canvas pixel.  M_B marks points whose source lies inside A's
-    window.  Rotating B back by theta and moving it by -s recovers A's
-    geometry, so an alignment sweep should return an angle near theta and a
-    displacement near s.  Draw order: field, noise, shift, angle,
-    permutation."""
+def rotated_intensities(rng, sigma, n, margin, shift_range, noise_sd):
+    """Intensity images: A = F on the window, B(p) = cos(2.5 F(src(p))) +
+    noise with src(p) = R(-theta)(p - c) + c - s, evaluated in FP64 and
+    rounded to the nearest canvas pixel; M_B marks points whose source lies
+    inside A's window.  Rotating B back by theta and moving it by -s
+    recovers A's geometry.  Draw order: field, noise, shift, angle.
+    Returns (A, B, M_B, s, theta) with A, B in FP64."""
     canvas = field(rng, sigma, (n + 2 * margin, n + 2 * margin))
     noise = rng.standard_normal((n, n))
     s = tuple(int(v) for v in rng.integers(-shift_range, shift_range + 1,
                                            size=2))
     theta = float(rng.uniform(0.0, 360.0))
-    perm = rng.permutation(q)
     fa = canvas[margin:margin + n, margin:margin + n]
     c = (n - 1) / 2.0
     th = math.radians(theta)
@@ -124,11 +122,21 @@ def rotated_pair(rng, sigma, n, q, margin, shift_range, noise_sd):
     inside = (ix >= 0) & (ix < n) & (iy >= 0) & (iy < n)
     cy = np.clip(iy + margin, 0, n + 2 * margin - 1)
     cx = np.clip(ix + margin, 0, n + 2 * margin - 1)
-    fb = canvas[cy, cx]
+    fb = np.cos(2.5 * canvas[cy, cx]) + noise_sd * noise
+    return fa, fb, inside.astype(np.uint8), s, theta
+
+
+def rotated_pair(rng, sigma, n, q, margin, shift_range, noise_sd):
+    """rotated_intensities quantised: A = qq(F), B = perm(qq(cos(2.5 F(src))
+    + noise)) over the footprint M_B, perm a seeded relabelling drawn after
+    the angle."""
+    fa, fb, inside, s, theta = rotated_intensities(rng, sigma, n, margin,
+                                                   shift_range, noise_sd)
+    perm = rng.permutation(q)
     a = qq(fa, q)
-    bl = qq(np.cos(2.5 * fb) + noise_sd * noise, q, inside)
+    bl = qq(fb, q, inside.astype(bool))
     b = perm[bl].astype(np.uint8)
-    return a, b, inside.astype(np.uint8), s, theta
+    return a, b, inside, s, theta
 
 
 def config3(n_angles: int = 180, size: int = 512, q: int = 16):
@@ -155,6 +163,18 @@ def table1_pair(n: int, q: int = 16):
     a, b, mb, s, theta = rotated_pair(rng, 4.0, n, q, n // 2, n // 10, 0.2)
     return dict(name=f"table1-{n}x{n}-q{q}", A=a, MA=np.ones((n, n), np.uint8),
                 B=b, MB=mb, qa=q, qb=q, shift=s, theta_deg=theta)
+
+
+def table1_intensities(n: int):
+    """Intensity (FP32) version of table1_pair for the whole Alg. 1
+    pipeline, quantisation included: A = F, B = cos(2.5 F(src)) + 0.2 N(0,1)
+    on the rotation footprint M_B (0 outside), blur sigma 4, shift within
+    n/10."""
+    rng = np.random.default_rng(seed_for(7, n))
+    fa, fb, mb, s, theta = rotated_intensities(rng, 4.0, n, n // 2, n // 10, 0.2)
+    fb = np.where(mb == 1, fb, 0.0)
+    return dict(name=f"table1-intensity-{n}x{n}", A=fa.astype(np.float32),
+                B=fb.astype(np.float32), MB=mb, shift=s, theta_deg=theta)
 
 
 def config4():

@@ -331,6 +331,24 @@ def test_window_validation_and_fft_sides(cm):
     assert plan_status(cm, d) == cm.CMIF_ERR_UNSUPPORTED
 
 
+def test_kmeans_validates_before_device_work(cm):
+    lib = cm._lib
+    P = 0x1000  # never dereferenced: every call below fails validation
+    E = cm.CMIF_ERR_INVALID_ARGUMENT
+    ok = dict(image=P, mask=None, n=100, m=1, k=4, init=P, batches=P, iters=5,
+              batch=10, centers=P, labels=P, bad=None, stream=None)
+    def call(**kw):
+        d = dict(ok, **kw)
+        return lib.cmif_kmeans(d["image"], d["mask"], d["n"], d["m"], d["k"],
+                               d["init"], d["batches"], d["iters"], d["batch"],
+                               d["centers"], d["labels"], d["bad"], d["stream"])
+    for bad in [dict(image=None), dict(centers=None), dict(labels=None),
+                dict(n=0), dict(k=0), dict(k=65), dict(m=0), dict(m=9),
+                dict(iters=-1), dict(iters=100001), dict(batches=None),
+                dict(batch=0), dict(batch=8193)]:
+        assert call(**bad) == E, bad
+
+
 def test_status_strings(cm):
     seen = set()
     for s in range(8):
