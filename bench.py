@@ -231,6 +231,38 @@ def table1_context(cm, torch, np, synth, dev):
                 "the GPU k-means")
 
 
+def template_bench(cm, torch, np, synth, dev, reps=5):
+    """The paper's run-time experiment shape: reference side 256 .. 2048,
+    floating image half of it, the CMIF map over every placement of the
+    floating image inside the reference (a displacement window), Q 16,
+    FP32-rounded, one angle.  Median time per map (cmif_compute of MI and N)
+    and the planted offset."""
+    out = []
+    for ref in (256, 512, 1024, 2048):
+        c = synth.template_pair(ref)
+        half = ref // 2
+        w = c["window"]
+        plan = cm.Plan([(ref, ref, half, half)], 16, 16, windows=[w])
+        A, B = dev(c["A"]), dev(c["B"])
+        res = plan.compute(A, None, B, None, mi=True, n=True, best=True)
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            res = plan.compute(A, None, B, None, mi=True, n=True, best=True)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        b = res["best"][0]
+        row = dict(reference=ref, floating=half, map=[half + 1, half + 1],
+                   fft=plan.info()["fft_h"], ms_per_map=round(float(np.median(times)), 3),
+                   found=[-b["dy"], -b["dx"]], planted=list(c["offset"]))
+        out.append(row)
+        del plan
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +276,8 @@ def main():
     ap.add_argument("--no-soft", action="store_true",
                     help="skip the soft-membership batch")
     ap.add_argument("--soft-steps", type=int, default=5)
+    ap.add_argument("--no-template", action="store_true",
+                    help="skip the template-matching maps")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the paper-shaped two-stage alignments")
     ap.add_argument("--no-stress", action="store_true",
@@ -394,6 +428,11 @@ def main():
                       (best["angle_index"], best["dy"], best["dx"]))
         del wplan
 
+    template = None
+    if not args.no_template:
+        print("[bench] template matching", file=sys.stderr, flush=True)
+        template = template_bench(cm, torch, np, synth, dev)
+
     table1 = None
     if not args.no_table1:
         table1 = table1_context(cm, torch, np, synth, dev)
@@ -458,6 +497,7 @@ def main():
                                   if plain else None),
         "window_sweep": window,
         "precision_stress": stress,
+        "template_matching": template,
         "paper_table1_context": table1,
         "soft": soft,
         "launch_shapes": {k: info1[k] for k in ("rows_per_wg", "labels_per_team",

@@ -177,6 +177,26 @@ def table1_intensities(n: int):
                 B=fb.astype(np.float32), MB=mb, shift=s, theta_deg=theta)
 
 
+def template_pair(ref: int, q: int = 16):
+    """Template matching as in the paper's run-time experiment: a ref x ref
+    reference and a floating image of half the side cut from it at a seeded
+    offset (every placement of the floating image inside the reference is a
+    candidate), blur sigma 4, the floating image passed through
+    cos(2.5 .) + 0.2 N(0,1) and relabelled.  The displacement pairing A(x)
+    with B(x + chi) puts the floating image at chi = -offset."""
+    rng = np.random.default_rng(seed_for(8, ref))
+    f = field(rng, 4.0, (ref, ref))
+    half = ref // 2
+    off = tuple(int(v) for v in rng.integers(0, ref - half + 1, size=2))
+    noise = rng.standard_normal((half, half))
+    perm = rng.permutation(q)
+    a = qq(f, q)
+    crop = f[off[0]:off[0] + half, off[1]:off[1] + half]
+    b = perm[qq(np.cos(2.5 * crop) + 0.2 * noise, q)].astype(np.uint8)
+    return dict(name=f"template-{ref}-{half}-q{q}", A=a, B=b, qa=q, qb=q,
+                offset=off, window=(-(ref - half), 0, -(ref - half), 0))
+
+
 def config4():
     """1024x1024, Q=16, blur sigma 6, B = quantised cos(2.5 f) + 0.2 N(0,1)
     moved by a seeded shift in [-8, 8]^2; all-ones masks (overlap counts up
