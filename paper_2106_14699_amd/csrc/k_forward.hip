@@ -26,8 +26,13 @@ __device__ __forceinline__ int floordiv_pos_pow2(long long a, int shift) {
   return (int)(a >> shift);
 }
 
+// Lanes of the forward row kernel: up to four teams, at most 512 (at 1024
+// lanes the launch bound leaves 128 registers per lane and the 2048-point
+// FP64 kernel spilled).
+constexpr int fwd_rows_lanes(int team) { return 4 * team <= 512 ? 4 * team : 512; }
+
 template <typename T, int P, int TEAM>
-__global__ void __launch_bounds__(4 * TEAM)
+__global__ void __launch_bounds__(fwd_rows_lanes(TEAM))
 k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
            const float* __restrict__ memb, int H, int W, int Q, int label0,
            RotArgs rot,
@@ -207,7 +212,7 @@ static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
   int nteams = npacks;
   const int max_teams_lds = (int)(65536 / per_team) > 0 ? (int)(65536 / per_team) : 1;
   if (nteams > max_teams_lds) nteams = max_teams_lds;
-  if (nteams > 4) nteams = 4;  // matches the kernel's launch bound
+  if (nteams > fwd_rows_lanes(TEAM) / TEAM) nteams = fwd_rows_lanes(TEAM) / TEAM;
   if (nteams < 1) nteams = 1;
   const size_t shm = per_team * nteams;
   auto fn = k_fwd_rows<T, P, TEAM>;
