@@ -133,3 +133,28 @@ def test_window_shrinks_fft_and_aligns(gpu, oracle):
         assert b["n"] == o["n"][i, j]
         assert abs(b["mi"] - o["mi"][i, j]) <= MI_TOL
     assert r["stats"]["label_errors"] == 0
+
+
+def test_template_matching_window(gpu, oracle):
+    """The paper's run-time experiment shape at a small side: a 128 x 128
+    reference, the floating image half of it cut at a seeded offset, the
+    map over every placement (window [-(64), 0]^2, FFT 128 instead of 256
+    for the full set); map equal to the oracle's cut, offset recovered."""
+    cm, torch = gpu
+    c = synth.template_pair(128)
+    w = c["window"]
+    plan = cm.Plan([(128, 128, 64, 64)], 16, 16, windows=[w])
+    assert (plan.info()["fft_h"], plan.info()["fft_w"]) == (128, 128)
+    say(f"[gpu] template 128/64 offset {c['offset']}")
+    r = plan.compute(dev(torch, c["A"]), None, dev(torch, c["B"]), None,
+                     mi=True, n=True, counts=True, best=True)
+    ones_a = np.ones_like(c["A"])
+    ones_b = np.ones_like(c["B"])
+    o = _cut(oracle.cmif_direct(c["A"], ones_a, c["B"], ones_b, 16, 16,
+                                counts=True), 128, 128, w)
+    assert np.array_equal(r["n"][0][0].cpu().numpy(), o["n"])
+    assert np.all(o["n"] == 64 * 64)  # every placement overlaps fully
+    assert np.array_equal(r["counts"][0][0].cpu().numpy(), o["counts"])
+    assert np.abs(r["mi"][0][0].cpu().numpy() - o["mi"]).max() <= MI_TOL
+    b = r["best"][0]
+    assert (-b["dy"], -b["dx"]) == tuple(c["offset"]), (b, c["offset"])
