@@ -119,9 +119,9 @@ def soft_bench(cm, torch, np, synth, steps):
             lk = torch.logsumexp(m[elig[k]] / cfg["temperature"], dim=0)
             lk.backward()
             grads.append(m.grad[None])
-            loss += float(lk)
+            loss = loss + lk.detach()
         ga, gb = plan.backward(A, MA, B, MB, grads)
-        return loss, ga, gb
+        return float(loss), ga, gb
 
     step()
     torch.cuda.synchronize()

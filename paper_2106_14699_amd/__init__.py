@@ -318,14 +318,17 @@ class Plan:
             self._keep.append(win)
             d.window = ctypes.cast(win, ctypes.POINTER(ctypes.c_int32))
         self.handle = cmif_plan(d)
+        # kept for __del__: module globals may already be gone at exit
+        self._free = _lib.cmif_plan_free
         self.persistent_bytes, self.scratch_bytes = cmif_workspace_size(
             self.handle)
         self._ws = None
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
-            cmif_plan_free(h)
+        free = getattr(self, "_free", None)
+        if h and free is not None:
+            free(h)  # argtypes convert the int handle
             self.handle = None
 
     def window(self, p: int = 0):
