@@ -175,7 +175,7 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
   L.fa = take(qa * half * g.ph * E);
   L.xb = take(nb * qb * half * g.hb * E);
   L.fb = take(nb * qb * half * g.ph * E);
-  L.z = take(nb * qa * qb * half * g.sh * E);
+  L.z = take(nb * z_pair_slots(qa * qb) * half * g.sh * E);
   L.mi = take(nb * (size_t)g.sh * g.sw * sizeof(double));
   L.n = take(nb * (size_t)g.sh * g.sw * sizeof(int32_t));
   L.maxn = take(nb * sizeof(uint32_t));
@@ -190,7 +190,7 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
     L.fa64 = take(qa * half * g.ph * E64);
     L.xb64 = take(nb * qb * half * g.hb * E64);
     L.fb64 = take(nb * qb * half * g.ph * E64);
-    L.z64 = take(cap * half * g.sh * E64);
+    L.z64 = take(z_pair_slots(cap) * half * g.sh * E64);
     L.cnt64 = take(cap * (size_t)g.sh * g.sw * sizeof(int32_t));
     L.items = take(cap * sizeof(int4));
     L.n_items = take(sizeof(uint32_t));
@@ -203,7 +203,7 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
     L.pl_fa = take((qa + 1) * half * g.ph * E64);
     L.pl_fb = take((qb + 1) * half * g.ph * E64);
     L.pl_y = take(half * g.ph * E64);
-    L.pl_z = take(half * g.sh * E64);
+    L.pl_z = take(z_pair_slots(1) * half * g.sh * E64);
     L.pl_maps = take((1 + qa + qb + qa * qb) * (size_t)g.sh * g.sw * sizeof(double));
   }
   if (P.d.mode == CMIF_MODE_SOFT) {
@@ -212,7 +212,7 @@ ScratchLayout layout_for(const cmif_plan_s& P, const PairPlan& g) {
     L.ov_fa = take(half * g.ph * E64);
     L.ov_xb = take(nb * half * g.hb * E64);
     L.ov_fb = take(nb * half * g.ph * E64);
-    L.ov_z = take(nb * half * g.sh * E64);
+    L.ov_z = take(nb * z_pair_slots(1) * half * g.sh * E64);
     if (P.d.flags & CMIF_FLAG_SAVE_FOR_BACKWARD) {
       L.zg = take(qa * qb * half * g.sh * E);
       L.gh = take(qa * qb * half * g.ph * E);
@@ -386,7 +386,7 @@ cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout&
   pc.fb_label_stride = (long long)half * g.ph;
   pc.QA = 1; pc.QB = 1; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
   pc.tiles = half / tile_width<double>(); pc.nb = nb; pc.Z = z;
-  pc.z_angle_stride = (long long)half * g.sh;
+  pc.z_angle_stride = (long long)z_pair_slots(1) * half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh;
   pc.tw = twiddles<double>(P, pers, g.ph); pc.xcd = P.xcd;
   STAGE(ST_PAIR_COLS, nb * (double)half * (g.ph + g.sh) * sizeof(C64),
@@ -480,7 +480,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pc.fb_label_stride = (long long)half * g.ph;
     pc.QA = qa; pc.QB = qb; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
     pc.tiles = tiles; pc.nb = nb; pc.Z = z;
-    pc.z_angle_stride = (long long)qa * qb * half * g.sh;
+    pc.z_angle_stride = (long long)z_pair_slots(qa * qb) * half * g.sh;
     pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h; pc.xcd = P.xcd;
     // A's spectra once per launch, B's once per angle, every pair's columns
     STAGE(ST_PAIR_COLS,
@@ -1045,7 +1045,7 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
   pc.fb_label_stride = (long long)half * g.ph;
   pc.QA = qa; pc.QB = qb; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
   pc.tiles = tiles; pc.nb = 1; pc.Z = z;
-  pc.z_angle_stride = (long long)qa * qb * half * g.sh;
+  pc.z_angle_stride = (long long)z_pair_slots(qa * qb) * half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh; pc.tw = twiddles<T>(P, pers, g.ph);
   pc.xcd = P.xcd;
   const double zbytes = (double)qa * qb * half * g.sh * sizeof(CT);

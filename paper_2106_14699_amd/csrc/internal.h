@@ -4,7 +4,8 @@
 // HBM layouts (per image pair; complex<T> = float2 or double2):
 //   row spectra  X[label][tile][y][TW]      tile = k_x / TW, y in [0, H)
 //   2D spectra   F[label][c][k_y]           c in [0, P_w/2), k_y in [0, P_h)
-//   pair columns Z[a*Q_B+b][tile][i][TW]    i = map row in [0, S_h)
+//   pair columns Z: pair p = a*Q_B+b, tile, map row i in [0, S_h), with
+//                pairs stored two by two (see z_pair_offset)
 // where TW = 64 B / sizeof(complex<T>) (8 for FP32, 4 for FP64), so one
 // (tile, row) record is one 64-byte segment.  Column c = 0 holds the two
 // real-input special frequencies packed as one complex value: the k_x = 0
@@ -40,6 +41,26 @@ struct ArgPartial {
 
 template <typename T>
 constexpr int tile_width() { return 64 / (2 * (int)sizeof(T)); }
+
+// Z layout: pairs are stored two by two, interleaved per (tile, map row):
+// the 64-byte segment (tile t, row i) of pair p sits at
+//   (p / 2) * 2 * pair_elems + t * 2 S_h TW + i * 2 TW + (p % 2) * TW
+// (pair_elems = (P_w / 2) S_h elements), so one 128-byte line holds row i
+// of both pairs that a row transform packs together.  Z buffers and
+// per-angle strides hold an even number of pair slots (z_pair_slots).
+template <typename T>
+__host__ __device__ constexpr long long z_row_offset(int i) {
+  return (long long)i * 2 * tile_width<T>();
+}
+template <typename T>
+__host__ __device__ constexpr long long z_pair_offset(int p, long long pair_elems) {
+  return (long long)(p >> 1) * 2 * pair_elems + (long long)(p & 1) * tile_width<T>();
+}
+template <typename T>
+__host__ __device__ constexpr int z_tile_stride(int sh) {
+  return sh * 2 * tile_width<T>();
+}
+__host__ __device__ constexpr int z_pair_slots(int n) { return (n + 1) & ~1; }
 
 // Lanes per FFT team: at most 8 points per lane (radix-8 stages), so a
 // 1024-point transform is spread over two waves and 2048 over four.
