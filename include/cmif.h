@@ -339,8 +339,7 @@ typedef struct cmif_plan_info {
   int32_t labels_per_team;    /* pair row kernel: labels of B per team (0:
                                  the default shape) */
   int32_t xcd_grouping;       /* pair column kernel: XCD-grouped order (1)
-                                 or launch order (0); the default is 1 for
-                                 FP64 plans and 2048-point columns */
+                                 or launch order (0, the default) */
   int32_t tuned;              /* 0 default shapes, 1 timed, 2 from the cache */
   int32_t tune_runs;          /* eager passes spent timing candidates */
   int32_t reserved;

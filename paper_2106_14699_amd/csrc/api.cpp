@@ -1418,10 +1418,10 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   size_t smax = 0;
   for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);
   P->scratch_bytes = smax;
-  // default column order: XCD-grouped where its F_B re-reads cost time (FP64
-  // spectra, 2048-point columns; measured 7-12 % faster there), launch
-  // order otherwise (at FP32 P <= 1024 it was 1-3 % faster)
-  P->def_xcd = (d->precision == CMIF_PREC_FP64 || P->pairs[0].ph >= 2048) ? 1 : 0;
+  // default column order: launch order (with Z's non-temporal stores and
+  // interleaved pairs the XCD-grouped order measured 1-10 % slower at every
+  // size and precision; it stays a tuner candidate)
+  P->def_xcd = 0;
   P->xcd = P->def_xcd;
   if (tunable(P)) {
     P->tune_key = tune_key(P);
