@@ -42,23 +42,33 @@ struct ArgPartial {
 template <typename T>
 constexpr int tile_width() { return 64 / (2 * (int)sizeof(T)); }
 
-// Z layout: pairs are stored two by two, interleaved per (tile, map row):
-// the 64-byte segment (tile t, row i) of pair p sits at
+// Z layout (FP32 up to P = 1024): pairs are stored two by two, interleaved
+// per (tile, map row): the 64-byte segment (tile t, row i) of pair p sits at
 //   (p / 2) * 2 * pair_elems + t * 2 S_h TW + i * 2 TW + (p % 2) * TW
 // (pair_elems = (P_w / 2) S_h elements), so one 128-byte line holds row i
-// of both pairs that a row transform packs together.  Z buffers and
-// per-angle strides hold an even number of pair slots (z_pair_slots).
-template <typename T>
+// of both pairs that a row transform packs together.  Elsewhere (FP64, and
+// FP32 at 2048 points, where the column kernel writes a tile as 32-byte
+// pieces and the interleave measured slower) one pair after the other:
+//   p * pair_elems + t * S_h TW + i * TW.
+// Z buffers and per-angle strides hold an even number of pair slots
+// (z_pair_slots).
+template <typename T, int P>
+__host__ __device__ constexpr int z_group() {
+  return sizeof(T) == 4 && P <= 1024 ? 2 : 1;
+}
+template <typename T, int P>
 __host__ __device__ constexpr long long z_row_offset(int i) {
-  return (long long)i * 2 * tile_width<T>();
+  return (long long)i * z_group<T, P>() * tile_width<T>();
 }
-template <typename T>
+template <typename T, int P>
 __host__ __device__ constexpr long long z_pair_offset(int p, long long pair_elems) {
-  return (long long)(p >> 1) * 2 * pair_elems + (long long)(p & 1) * tile_width<T>();
+  return z_group<T, P>() == 2
+             ? (long long)(p >> 1) * 2 * pair_elems + (long long)(p & 1) * tile_width<T>()
+             : (long long)p * pair_elems;
 }
-template <typename T>
+template <typename T, int P>
 __host__ __device__ constexpr int z_tile_stride(int sh) {
-  return sh * 2 * tile_width<T>();
+  return sh * z_group<T, P>() * tile_width<T>();
 }
 __host__ __device__ constexpr int z_pair_slots(int n) { return (n + 1) & ~1; }
 

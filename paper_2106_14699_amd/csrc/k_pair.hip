@@ -101,7 +101,7 @@ __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* sme
   float4* z4 = reinterpret_cast<float4*>(zp);
   for (int e = threadIdx.x; e < sh * CPW / EV; e += blockDim.x) {
     const int i = (e * EV) / CPW, col = (e * EV) % CPW;
-    store_stream16(z4 + (z_row_offset<T>(i) + part * CPW + col) / EV,
+    store_stream16(z4 + (z_row_offset<T, P>(i) + part * CPW + col) / EV,
                    *reinterpret_cast<const float4*>(
                        &stage[i * CPW + (col ^ pc_swz<CPW, EV>(i))]));
   }
@@ -127,7 +127,7 @@ __device__ __forceinline__ void pair_cols_run(
       for (int q = 0; q < R; ++q) v[q] = fb_col[lane + TEAM * q];
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM>(
-          v, smem, z_base + z_pair_offset<T>(zpair0 + b - b_begin, z_pair_stride), ha,
+          v, smem, z_base + z_pair_offset<T, P>(zpair0 + b - b_begin, z_pair_stride), ha,
           hb, sh, team, part, lane);
     }
     return;
@@ -154,7 +154,7 @@ __device__ __forceinline__ void pair_cols_run(
       }
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM>(
-          v, smem, z_base + z_pair_offset<T>(zpair0 + b - b_begin, z_pair_stride), ha,
+          v, smem, z_base + z_pair_offset<T, P>(zpair0 + b - b_begin, z_pair_stride), ha,
           hb, sh, team, part, lane);
     }
   } else {
@@ -175,7 +175,7 @@ __device__ __forceinline__ void pair_cols_run(
       }
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM>(
-          v, smem, z_base + z_pair_offset<T>(zpair0 + b - b_begin, z_pair_stride), ha,
+          v, smem, z_base + z_pair_offset<T, P>(zpair0 + b - b_begin, z_pair_stride), ha,
           hb, sh, team, part, lane);
     }
   }
@@ -215,7 +215,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     b_begin = 0;
     b_end = QB;
     zpair0 = a * QB;
-    z_base = Z + beta * z_angle_stride + (long long)(t / NPART) * z_tile_stride<T>(sh);
+    z_base = Z + beta * z_angle_stride + (long long)(t / NPART) * z_tile_stride<T, P>(sh);
   } else {
     // item list: workgroup (tile, item) runs one pair (angle, a, b) of the
     // list into slot `item` of Z
@@ -227,7 +227,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     b_begin = e.z;
     b_end = e.z + 1;
     zpair0 = it;
-    z_base = Z + (long long)(t / NPART) * z_tile_stride<T>(sh);
+    z_base = Z + (long long)(t / NPART) * z_tile_stride<T, P>(sh);
   }
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;

@@ -93,7 +93,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   };
 
   const T scale = (T)1 / ((T)ph * (T)P);
-  const int tile_stride = z_tile_stride<T>(sh);
+  const int tile_stride = z_tile_stride<T, P>(sh);
   const int b_first = team * BPW;
   const int nq = QA * QB;
   float maxres = 0.0f;
@@ -104,7 +104,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     for (int x = tid; x < 2 * P; x += NT) slot[x] = 0u;
     for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
     __syncthreads();
-    const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T>(i);
+    const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T, P>(i);
 
     uint32_t cb[BPW][R];
     double sab[R];
@@ -121,8 +121,8 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     {
       const int b0 = b_first, b1 = b0 + 1;
       if (b0 < QB)
-        load_raw<T, P, TEAM, SPLIT>(zrow + z_pair_offset<T>(b0, z_pair_stride),
-                                    zrow + z_pair_offset<T>(b1, z_pair_stride), b1 < QB,
+        load_raw<T, P, TEAM, SPLIT>(zrow + z_pair_offset<T, P>(b0, z_pair_stride),
+                                    zrow + z_pair_offset<T, P>(b1, z_pair_stride), b1 < QB,
                                     tile_stride, lane, nu0, nu1);
     }
     for (int a = 0; a < QA; ++a) {
@@ -147,8 +147,8 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
           const int nb0 = pk + 1 < BPW / 2 ? b0 + 2 : b_first;
           if (na < QA && nb0 < QB)
             load_raw<T, P, TEAM, SPLIT>(
-                zrow + z_pair_offset<T>(na * QB + nb0, z_pair_stride),
-                zrow + z_pair_offset<T>(na * QB + nb0 + 1, z_pair_stride),
+                zrow + z_pair_offset<T, P>(na * QB + nb0, z_pair_stride),
+                zrow + z_pair_offset<T, P>(na * QB + nb0 + 1, z_pair_stride),
                 nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
         }
         row_fft(w);
@@ -311,7 +311,7 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
   const int tid = threadIdx.x, team = tid / TEAM, lane = tid % TEAM;
   C2<T>* lds = exch + team * lds_elems(P);
   const T scale = (T)1 / ((T)ph * (T)P);
-  const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T>(i);
+  const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T, P>(i);
   const int npairs = QA * QB;
   const int nq = items ? (int)*n_items : npairs;  // slots of Z to emit
   if (nq == 0) return;
@@ -325,9 +325,9 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
     const bool has0 = p0 < nq, has1 = p1 < nq;
     C2<T> w[R];
     if (has0) {
-      load_pack<T, P, TEAM>(zrow + z_pair_offset<T>(p0, z_pair_stride),
-                            zrow + z_pair_offset<T>(p1, z_pair_stride), has1,
-                            z_tile_stride<T>(sh), lane, w);
+      load_pack<T, P, TEAM>(zrow + z_pair_offset<T, P>(p0, z_pair_stride),
+                            zrow + z_pair_offset<T, P>(p1, z_pair_stride), has1,
+                            z_tile_stride<T, P>(sh), lane, w);
     } else {
 #pragma unroll
       for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);

@@ -65,12 +65,12 @@ k_soft_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   FftTw<T, P, TEAM> ftw;
   fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
   const T scale = (T)1 / ((T)ph * (T)P);
-  const int tile_stride = z_tile_stride<T>(sh);
+  const int tile_stride = z_tile_stride<T, P>(sh);
   const int b_first = team * BPW;
   const long long plane = (long long)sh * sw;
   const long long mrow = (long long)i * sw;
   T* sv = save ? save + beta * save_angle_stride : nullptr;
-  const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T>(i);
+  const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T, P>(i);
 
   // the fold loops below give every x to the same thread: no barrier needed
   for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0.0; }
@@ -92,8 +92,8 @@ k_soft_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
       const bool has0 = b0 < QB, has1 = b1 < QB;
       C2<T> w[R];
       if (has0) {
-        load_pack<T, P, TEAM>(zrow + z_pair_offset<T>(a * QB + b0, z_pair_stride),
-                              zrow + z_pair_offset<T>(a * QB + b1, z_pair_stride),
+        load_pack<T, P, TEAM>(zrow + z_pair_offset<T, P>(a * QB + b0, z_pair_stride),
+                              zrow + z_pair_offset<T, P>(a * QB + b1, z_pair_stride),
                               has1, tile_stride, lane, w);
       } else {
 #pragma unroll
@@ -219,9 +219,9 @@ k_soft_grad_rows(const C2<T>* __restrict__ Z, long long z_pair_stride, int QA,
     const bool has0 = p0 < nq, has1 = p1 < nq;
     C2<T> w[R];
     if (has0) {
-      load_pack<T, P, TEAM>(Z + z_pair_offset<T>(p0, z_pair_stride) + z_row_offset<T>(i),
-                            Z + z_pair_offset<T>(p1, z_pair_stride) + z_row_offset<T>(i),
-                            has1, z_tile_stride<T>(sh), lane, w);
+      load_pack<T, P, TEAM>(Z + z_pair_offset<T, P>(p0, z_pair_stride) + z_row_offset<T, P>(i),
+                            Z + z_pair_offset<T, P>(p1, z_pair_stride) + z_row_offset<T, P>(i),
+                            has1, z_tile_stride<T, P>(sh), lane, w);
     } else {
 #pragma unroll
       for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
