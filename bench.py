@@ -79,16 +79,47 @@ def read_traffic(stage):
     return float(m_b.group(1))
 
 
-def cpu_baseline(c):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(c, np):
+    """The oracle (direct method) on one angle's full map on all host
+    threads, plus a one-thread rate measured on a 256x256 crop of the same
+    pair and scaled to the full map by the pixel visits sum_chi N(chi) =
+    |M_A| |M_B'| that the direct method makes."""
     import oracle
     nt = oracle.max_threads()
     B, MB = oracle.warp_nn(c["B"], c["MB"], c["angles"][0])
     t0 = time.perf_counter()
     oracle.cmif_direct(c["A"], c["MA"], B, MB, c["qa"], c["qb"])
     dt = time.perf_counter() - t0
+    visits = float(c["MA"].astype(np.int64).sum()) * float(MB.astype(np.int64).sum())
+    crop = (slice(128, 384), slice(128, 384))
+    va = float(c["MA"][crop].astype(np.int64).sum()) * float(MB[crop].astype(np.int64).sum())
+    t1 = time.perf_counter()
+    oracle.cmif_direct(c["A"][crop], c["MA"][crop], B[crop], MB[crop], c["qa"],
+                       c["qb"], nthreads=1)
+    d1 = time.perf_counter() - t1
+    one = va / d1
     return dict(value=1.0 / dt, unit="maps/s", cores=nt, kind="oracle",
                 sample=f"1 of 180 angles (full {2 * 512 - 1}x{2 * 512 - 1} map,"
-                       f" direct method) in {dt:.1f} s on {nt} threads")
+                       f" direct method, {visits:.3g} pixel visits) in "
+                       f"{dt:.1f} s on {nt} threads",
+                cpu_model=cpu_model(),
+                visits_per_s=round(visits / dt, 1),
+                one_thread=dict(value=round(one / visits, 6), unit="maps/s",
+                                visits_per_s=round(one, 1),
+                                sample="256x256 crops of A and the rotated B "
+                                       f"({va:.3g} visits) in {d1:.1f} s on "
+                                       "1 thread, scaled by visits"))
 
 
 def soft_bench(cm, torch, np, synth, steps):
@@ -139,13 +170,46 @@ def soft_bench(cm, torch, np, synth, steps):
                      "(host syncs included)")
 
 
-def stress_bench(cm, torch, np, synth, dev, reps=3):
+class OracleMap:
+    """The oracle's full direct map of the 1024x1024 stress pair, computed
+    on host threads in the background (the C oracle releases the GIL) while
+    the GPU sections run."""
+
+    def __init__(self, c, nthreads):
+        import threading
+        self.c = c
+        self.nthreads = nthreads
+        self.res = None
+        self.err = None
+        self.seconds = None
+        self.t = threading.Thread(target=self._run, daemon=True)
+        self.t.start()
+
+    def _run(self):
+        try:
+            import oracle
+            t0 = time.perf_counter()
+            c = self.c
+            self.res = oracle.cmif_direct(c["A"], c["MA"], c["B"], c["MB"],
+                                          c["qa"], c["qb"], digest=True,
+                                          nthreads=self.nthreads)
+            self.seconds = time.perf_counter() - t0
+        except Exception as e:  # reported in the bench line
+            self.err = repr(e)
+
+    def get(self):
+        self.t.join()
+        return self.res
+
+
+def stress_bench(cm, torch, np, synth, dev, reps=3, omap=None):
     """1024x1024, Q 16, all-ones masks (joint counts up to 2^20), FFT 2048:
     the FP32-rounded path with its residual check and FP64 re-run against
-    the full-FP64 path on the same GPU.  Median of `reps` computes each
+    the full-FP64 path on the same GPU, and both against the oracle's full
+    direct map (N, digests, max |dMI|).  Median of `reps` computes each
     (MI, N and digests emitted)."""
     print("[bench] precision stress 1024x1024", file=sys.stderr, flush=True)
-    c = synth.config4()
+    c = synth.config4() if omap is None else omap.c
     n = 1024
     ins = [dev(c[k]) for k in ("A", "MA", "B", "MB")]
     out = {}
@@ -170,6 +234,25 @@ def stress_bench(cm, torch, np, synth, dev, reps=3):
     same_digests = bool(torch.equal(r32["digest"][0], r64["digest"][0]))
     st = r32["stats"]
     b32, b64 = r32["best"][0], r64["best"][0]
+    vs_oracle = None
+    if omap is not None:
+        print("[bench] waiting for the oracle's 1024x1024 map", file=sys.stderr,
+              flush=True)
+        o = omap.get()
+        if o is not None:
+            n32 = r32["n"][0][0].cpu().numpy()
+            vs_oracle = dict(
+                max_abs_dmi_fp32=float(np.abs(r32["mi"][0][0].cpu().numpy() -
+                                              o["mi"]).max()),
+                max_abs_dmi_fp64=float(np.abs(r64["mi"][0][0].cpu().numpy() -
+                                              o["mi"]).max()),
+                n_equal=bool(np.array_equal(n32, o["n"])),
+                digests_equal=bool(np.array_equal(
+                    r32["digest"][0][0].cpu().numpy().view(np.uint64),
+                    o["digest"])),
+                oracle_s=round(omap.seconds, 1), oracle_threads=omap.nthreads)
+        else:
+            vs_oracle = dict(error=omap.err)
     return dict(workload="1024x1024 uint8, Q_A=Q_B=16, all-ones masks, one "
                          "angle, full 2047x2047 map",
                 fft=out["fp32"]["fft"],
@@ -179,6 +262,9 @@ def stress_bench(cm, torch, np, synth, dev, reps=3):
                 max_residual=st["max_residual"],
                 flagged_pairs=st["flagged_pairs"],
                 fallback_pairs=st["fallback_pairs"],
+                fallback_overflow=st["fallback_overflow"],
+                unresolved_pairs=st["unresolved_pairs"],
+                vs_oracle=vs_oracle,
                 max_abs_dmi_vs_fp64=dmi, digests_equal=same_digests,
                 same_best=(b32["dy"], b32["dx"]) == (b64["dy"], b64["dx"]),
                 planted_shift=list(c["shift"]), best=[b32["dy"], b32["dx"]])
@@ -356,6 +442,18 @@ def main():
     eager_ms = sum(s["total_ms"] for s in stages) / stage_steps
     value = n_maps * 1000.0 / ms_per_step
     best = cm.best_from_bytes(bytes(out["best_raw"][0].cpu().numpy()))
+    # exactness of the timed calls: no flagged pair left without its FP64
+    # re-run (the last timed call's stats; every call has the same inputs)
+    hstats = cm.stats_from_raw(out["stats_raw"])
+    if hstats["unresolved_pairs"] != 0:
+        raise SystemExit(f"timed alignment left flagged pairs unresolved: {hstats}")
+
+    # the oracle's full map of the stress pair, on host threads while the
+    # remaining GPU sections run (two threads stay free for the GPU driver)
+    omap = None
+    if not args.no_stress and not args.no_cpu:
+        import oracle
+        omap = OracleMap(synth.config4(), max(1, oracle.max_threads() - 2))
 
     dom = max(stages, key=lambda s: s["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
@@ -443,7 +541,24 @@ def main():
 
     stress = None
     if not args.no_stress:
-        stress = stress_bench(cm, torch, np, synth, dev)
+        stress = stress_bench(cm, torch, np, synth, dev, omap=omap)
+
+    # attainable HBM bandwidth of a plain device copy (context for the
+    # roofline): 1 GiB read + 1 GiB written per copy, median of 5
+    csrc = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    cts = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cdst.copy_(csrc)
+        e1.record()
+        torch.cuda.synchronize()
+        cts.append(e0.elapsed_time(e1))
+    copy_gbs = 2.0 * (1 << 30) / (float(np.median(cts)) * 1e-3) / 1e9
+    del csrc, cdst
 
     soft = None
     if not args.no_soft:
@@ -469,7 +584,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(c)
+        cpu = cpu_baseline(c, np)
         cpu["value"] = round(cpu["value"], 5)
 
     line = {
@@ -494,6 +609,16 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_copy": dict(gbs=round(copy_gbs, 1),
+                         frac_of_peak=round(copy_gbs / HBM_PEAK_GBS, 4),
+                         kernel_frac_of_copy=round(achieved / copy_gbs, 4),
+                         note="torch device copy of 1 GiB, read + write "
+                              "bytes, median of 5"),
+        "exactness": dict(unresolved_pairs=hstats["unresolved_pairs"],
+                          fallback_overflow=hstats["fallback_overflow"],
+                          flagged_pairs=hstats["flagged_pairs"],
+                          fallback_pairs=hstats["fallback_pairs"],
+                          max_residual=hstats["max_residual"]),
         "ms_per_step_median": round(float(np.median(step_ms)), 3),
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (round(plain["ms_per_step_median"] /

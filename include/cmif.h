@@ -185,7 +185,12 @@ typedef struct cmif_stats {
   float max_residual;         /* max |y - rint(y)| over used displacements of
                                  the FP32 stages (before any re-run) */
   uint32_t nonfinite_inputs;  /* SOFT: NaN/Inf memberships seen */
-  uint32_t reserved[2];
+  uint32_t unresolved_pairs;  /* items whose residual reached 0.25 but that
+                                 the FP64 re-run did not take (beyond its
+                                 capacity): their counts, and the MI of their
+                                 angle, are not guaranteed exact.  0 means
+                                 every count of the call is exact */
+  uint32_t reserved;
 } cmif_stats;
 
 /* One alignment result (Alg. 1 output): the angle index into the plan's

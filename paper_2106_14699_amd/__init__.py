@@ -74,7 +74,8 @@ class cmif_stats(ctypes.Structure):
                 ("fallback_overflow", ctypes.c_uint32),
                 ("max_residual", ctypes.c_float),
                 ("nonfinite_inputs", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("unresolved_pairs", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class cmif_best(ctypes.Structure):
@@ -119,6 +120,21 @@ class CmifError(RuntimeError):
         if detail:
             msg += f" ({detail})"
         super().__init__(msg)
+
+
+class CmifInexactError(CmifError):
+    """A call finished, but some label pairs whose FP32 rounding residual
+    reached 0.25 were not recomputed in FP64 (the plan's fallback capacity
+    was too small), so their counts are not guaranteed exact.  The results
+    are attached as `.results`."""
+
+    def __init__(self, where: str, stats: dict, results=None):
+        self.stats = stats
+        self.results = results
+        super().__init__(CMIF_OK, where,
+                         f"{stats['unresolved_pairs']} flagged label pairs "
+                         "beyond the FP64 re-run capacity; raise "
+                         "fallback_capacity, or pass allow_inexact=True")
 
 
 def _load_lib():
@@ -323,6 +339,8 @@ class Plan:
         self.persistent_bytes, self.scratch_bytes = cmif_workspace_size(
             self.handle)
         self._ws = None
+        self._forward_gen = 0        # cmif_compute calls made by this plan
+        self.recomputed_forwards = 0  # SoftCMIF backwards that re-ran theirs
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -413,11 +431,14 @@ class Plan:
 
     def compute(self, A, MA=None, B=None, MB=None, *, mi=True, n=True,
                 counts=False, digest=False, best=False, per_angle=False,
-                reuse=False):
+                reuse=False, allow_inexact=False):
         """CMIF maps for every pair and angle.  Returns a dict of lists (one
         entry per pair) of torch tensors, plus 'stats' (dict).  With
         reuse=True the output tensors belong to the plan and are overwritten
-        by its next call (stable pointers replay the captured graph)."""
+        by its next call (stable pointers replay the captured graph).
+        Raises CmifInexactError when flagged label pairs were left without
+        their FP64 re-run (stats['unresolved_pairs'] > 0), unless
+        allow_inexact=True."""
         torch = self._torch
         inp, keep = self._inputs(A, MA, B, MB)
         na = len(self.angles)
@@ -463,18 +484,24 @@ class Plan:
                                  for k in range(na)]
                                 for p in range(len(self.sizes))]
         del keep
+        self._forward_gen += 1
+        if res["stats"]["unresolved_pairs"] and not allow_inexact:
+            raise CmifInexactError("cmif_compute", res["stats"], res)
         return res
 
     def info(self) -> dict:
         return cmif_plan_query(self.handle)
 
     def align(self, A, MA=None, B=None, MB=None, *, per_angle=False,
-              sync=True):
+              sync=True, allow_inexact=False):
         """Alg. 1 over the plan's angles for every pair.  Returns a list of
         best dicts (and per-angle lists), plus stats.  The small result
         buffers belong to the plan (stable pointers replay the captured
         graph): with sync=False the returned raw tensors are overwritten by
-        the next call."""
+        the next call, and the caller checks stats_raw itself (see
+        stats_from_raw).  With sync=True, raises CmifInexactError when
+        flagged label pairs were left without their FP64 re-run, unless
+        allow_inexact=True."""
         torch = self._torch
         inp, keep = self._inputs(A, MA, B, MB)
         na = len(self.angles)
@@ -503,7 +530,14 @@ class Plan:
             res["per_angle"] = [[best_from_bytes(bytes(raw[p, k]))
                                  for k in range(na)]
                                 for p in range(len(self.sizes))]
+        if res["stats"]["unresolved_pairs"] and not allow_inexact:
+            raise CmifInexactError("cmif_align", res["stats"], res)
         return res
+
+
+def stats_from_raw(stats_t) -> dict:
+    """cmif_stats (a device or host uint8 tensor of its bytes) as a dict."""
+    return _stats_dict(stats_t)
 
 
 def cmif_kmeans(image, mask, n_pixels, channels, k, init_idx, batches, iters,
@@ -640,7 +674,14 @@ def _soft_cmif_function():
         [Q_A][H_A][W_A] and B [Q_B][H_B][W_B] (float32, on the plan's
         device) under masks MA, MB (uint8 or None); backward runs the
         library's adjoint.  The plan must be SOFT with SAVE_FOR_BACKWARD and
-        describe exactly one image pair."""
+        describe exactly one image pair.
+
+        The adjoint reads the per-displacement state that the plan's last
+        forward left in its persistent workspace.  Several forwards may share
+        one plan before their backwards run (a loss summed over pairs of one
+        size): each forward records the plan's forward count, and a backward
+        whose forward is no longer the plan's last one first runs that
+        forward again to restore its state."""
 
         @staticmethod
         def forward(ctx, A, B, plan, MA=None, MB=None):
@@ -648,6 +689,7 @@ def _soft_cmif_function():
             B = B.detach().contiguous()
             res = plan.compute(A, MA, B, MB, mi=True, n=False)
             ctx.plan = plan
+            ctx.gen = plan._forward_gen
             ctx.save_for_backward(A, B)
             ctx.masks = (MA, MB)
             return res["mi"][0]
@@ -657,6 +699,10 @@ def _soft_cmif_function():
             A, B = ctx.saved_tensors
             MA, MB = ctx.masks
             need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            if ctx.plan._forward_gen != ctx.gen:
+                # another forward on this plan overwrote the saved state
+                ctx.plan.compute(A, MA, B, MB, mi=False, n=False)
+                ctx.plan.recomputed_forwards += 1
             ga, gb = ctx.plan.backward(A, MA, B, MB, grad_mi, want_a=need_a,
                                        want_b=need_b)
             return (ga[0] if ga else None, gb[0] if gb else None, None, None,
@@ -704,4 +750,5 @@ def _stats_dict(stats_t):
                 fallback_pairs=s.fallback_pairs,
                 fallback_overflow=s.fallback_overflow,
                 max_residual=s.max_residual,
-                nonfinite_inputs=s.nonfinite_inputs)
+                nonfinite_inputs=s.nonfinite_inputs,
+                unresolved_pairs=s.unresolved_pairs)

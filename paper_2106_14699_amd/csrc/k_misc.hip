@@ -174,6 +174,10 @@ k_fb_list(const uint32_t* __restrict__ flags, int nb, int QA, int QB, int force,
         slot = (int32_t)pos;
         gate_l[beta] = 1u;
         if (digest) digest[idx] = 0ull;
+      } else if (flags[idx] != 0u && stats) {
+        // its residual reached 0.25 and it is not recomputed: its counts
+        // may be off by one
+        atomicAdd(&stats->unresolved_pairs, 1u);
       }
       ovr[idx] = slot;
     }
@@ -264,12 +268,14 @@ __global__ void k_plain_entropy(const double* __restrict__ joint,
     const double nr = fmax(rint(nmap[o]), 0.0);
     nn = (uint32_t)nr;
     double v = 0.0;
-    if (nn > 0u) {
+    // MI >= 0, and exactly 0 with one label on either side (as in the
+    // fused row pass)
+    if (nn > 0u && QA > 1 && QB > 1) {
       double sab = 0.0, sa = 0.0, sb = 0.0;
       for (int p = 0; p < QA * QB; ++p) sab += plain_xlog(joint[p * S + o]);
       for (int a = 0; a < QA; ++a) sa += plain_xlog(marg_a[a * S + o]);
       for (int b = 0; b < QB; ++b) sb += plain_xlog(marg_b[b * S + o]);
-      v = log2(nr) + (sab - sa - sb) / nr;
+      v = fmax(log2(nr) + (sab - sa - sb) / nr, 0.0);
     }
     mi[o] = v;
     n_out[o] = (int32_t)nn;

@@ -182,7 +182,9 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             e0max = fmaxf(e0max, (float)fabs(v0 - r0));
             e1max = fmaxf(e1max, (float)fabs(v1 - r1));
             const uint32_t n0 = (uint32_t)fmax(r0, (T)0);
-            const uint32_t n1 = (uint32_t)fmax(r1, (T)0);
+            // an odd Q_B leaves the last pack without a second pair: its
+            // imaginary part is transform noise and counts nothing
+            const uint32_t n1 = has1 ? (uint32_t)fmax(r1, (T)0) : 0u;
             cb[2 * pk][q] += n0;
             cb[2 * pk + 1][q] += n1;
             ca[q] += n0 + n1;
@@ -197,7 +199,8 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
           for (int q = 0; q < R; ++q) {
             if (circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
               const uint32_t n0 = (uint32_t)fmax(round_half_even<T>(w[q].x * scale), (T)0);
-              const uint32_t n1 = (uint32_t)fmax(round_half_even<T>(w[q].y * scale), (T)0);
+              const uint32_t n1 =
+                  has1 ? (uint32_t)fmax(round_half_even<T>(w[q].y * scale), (T)0) : 0u;
               if (n0 >= (uint32_t)kXlogN)
                 sab[q] += xlog2x_u32(n0, ltab) - xlt[kXlogN - 1];
               if (n1 >= (uint32_t)kXlogN)
@@ -258,8 +261,12 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         for (int g = 0; g < nteams; ++g)
           tsum += reinterpret_cast<const double*>(exch + g * lds_elems(P))[x];
         const uint32_t nn = n_l[x];
+        // MI >= 0 for any joint histogram, and one label on either side
+        // gives H_AB = H_B (or H_A) term by term, so MI = 0 exactly; the
+        // identity form can round to a few ulps on either side of those
         double mi = 0.0;
-        if (nn > 0u) mi = log2_u32(nn, ltab) + (tsum - sa_l[x]) / (double)nn;
+        if (nn > 0u && QA > 1 && QB > 1)
+          mi = fmax(log2_u32(nn, ltab) + (tsum - sa_l[x]) / (double)nn, 0.0);
         if (mi_out) mi_out[beta * mi_angle_stride + (long long)i * sw + j] = mi;
         if (n_out) n_out[beta * n_angle_stride + (long long)i * sw + j] = (int32_t)nn;
         nmax = nn > nmax ? nn : nmax;

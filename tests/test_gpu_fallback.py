@@ -112,7 +112,7 @@ def _stress(gpu, oracle, c, tag):
     say(f"{tag}: max residual {st['max_residual']:.4f} flagged "
         f"{st['flagged_pairs']} re-run {st['fallback_pairs']} overflow "
         f"{st['fallback_overflow']}")
-    assert st["fallback_overflow"] == 0
+    assert st["fallback_overflow"] == 0 and st["unresolved_pairs"] == 0
     assert st["fallback_pairs"] == st["flagged_pairs"]
     assert np.array_equal(g32["digest"][0], g64["digest"][0])
     assert np.array_equal(g32["n"][0], g64["n"][0])
@@ -136,6 +136,37 @@ def test_precision_stress_1024_q16(gpu, oracle):
     assert g["stats"]["max_residual"] < 0.25
     b = g["best"]
     assert (b["dy"], b["dx"]) == tuple(c["shift"])
+
+
+def test_precision_stress_1024_q16_full_oracle_map(gpu, oracle):
+    """The stress pair's FP32-rounded map against the oracle's full direct
+    map (every one of the 2047 x 2047 displacements, all 256 label pairs):
+    N bit-exact everywhere, all 256 count digests equal, MI within 1e-12
+    everywhere.  The oracle visits (1024^2)^2 pixel pairs (about half a
+    minute on 16 host threads)."""
+    import time
+    c = synth.config4()
+    g = run_compute(gpu, c, "fp32", counts=False, digest=True, best=True,
+                    tag="1024x1024-q16 full oracle map")
+    st = g["stats"]
+    assert st["unresolved_pairs"] == 0
+    say(f"[cpu] oracle direct map 1024x1024 q16 on {oracle.max_threads()} "
+        "threads")
+    t0 = time.perf_counter()
+    o = oracle.cmif_direct(c["A"], c["MA"], c["B"], c["MB"], 16, 16,
+                           digest=True)
+    say(f"[cpu] oracle done in {time.perf_counter() - t0:.1f} s")
+    assert np.array_equal(g["n"][0], o["n"]), "N map differs"
+    bad = np.argwhere(g["digest"][0] != o["digest"])
+    assert bad.size == 0, f"{len(bad)} label pairs' digests differ: {bad[:4]}"
+    err = float(np.abs(g["mi"][0] - o["mi"]).max())
+    say(f"max|dMI| vs oracle over the full map {err:.3e}; max residual "
+        f"{st['max_residual']:.4f}")
+    assert err <= MI_TOL
+    idx, v, _ = oracle.argmax(o["mi"], o["n"], 0.5)
+    b = g["best"]
+    assert (b["dy"], b["dx"]) == tuple(c["shift"])
+    assert divmod(idx, o["mi"].shape[1]) == (b["dy"] + 1023, b["dx"] + 1023)
 
 
 def test_precision_stress_1024_q2_full_overlap(gpu, oracle):

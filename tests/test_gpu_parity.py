@@ -92,14 +92,30 @@ def test_iid_labels_and_single_label(gpu, oracle):
     g = run_compute(gpu, c, "fp32", tag="iid")
     o = oracle.cmif_direct(c["A"], c["MA"], c["B"], c["MB"], 8, 8, counts=True)
     check_map(oracle, g, o)
-    c1 = dict(c, A=np.zeros_like(c["A"]), qa=1)
-    g1 = run_compute(gpu, c1, "fp32", counts=False, tag="qa=1")
-    assert np.abs(g1["mi"]).max() <= MI_TOL
-    # Alg. 1 keeps the identity when no angle has positive MI; values that are
-    # 0 in exact arithmetic may come out as +-1e-16, a near-tie under the
-    # 1e-12 acceptance rule
-    b = g1["best"]
-    assert b["angle_index"] == -1 or abs(b["mi"]) <= MI_TOL
+    # one label on either side: MI is exactly 0 everywhere (H_AB = H_A or
+    # H_B term by term), in the oracle and on the GPU, so Alg. 1 keeps the
+    # identity (angle index -1, chi = 0, I = 0)
+    for prec in ("fp32", "fp64"):
+        for side in ("a", "b"):
+            c1 = (dict(c, A=np.zeros_like(c["A"]), qa=1) if side == "a"
+                  else dict(c, B=np.zeros_like(c["B"]), qb=1))
+            g1 = run_compute(gpu, c1, prec, counts=False,
+                             tag=f"q{side}=1 {prec}")
+            o1 = oracle.cmif_direct(c1["A"], c1["MA"], c1["B"], c1["MB"],
+                                    c1["qa"], c1["qb"])
+            assert np.all(o1["mi"] == 0.0)
+            assert np.all(g1["mi"] == 0.0)
+            assert np.array_equal(g1["n"][0], o1["n"])
+            b = g1["best"]
+            assert (b["angle_index"], b["dy"], b["dx"], b["mi"]) == (-1, 0, 0, 0.0)
+    # an odd Q_B: the last row-transform pack carries one pair only, and its
+    # unused half must count nothing (N equals the oracle's everywhere)
+    c3 = synth.random_case(78, 61, 47, 55, 66, 5, 7, mask_density=0.7)
+    g3 = run_compute(gpu, c3, "fp32", tag="qb=7 odd")
+    o3 = oracle.cmif_direct(c3["A"], c3["MA"], c3["B"], c3["MB"], 5, 7,
+                            counts=True)
+    check_map(oracle, g3, o3)
+    assert g["mi"].min() >= 0.0 and g3["mi"].min() >= 0.0
 
 
 def test_label_out_of_range_reported(gpu, oracle):

@@ -301,6 +301,45 @@ def test_align_first_angle_wins_ties(oracle):
     assert r["angle_index"] == 0
 
 
+def test_align_starts_from_identity(oracle):
+    """Alg. 1 initialises the best transform to the identity with I = 0 and
+    replaces it only on a strictly larger MI: when no angle reaches a
+    positive MI (one label in A, so MI is 0 at every displacement), the
+    result is the identity (angle index -1, chi = 0, I = 0), not the first
+    angle's pick."""
+    rng = np.random.default_rng(3)
+    A = np.zeros((9, 11), np.uint8)
+    B = rng.integers(0, 3, size=(10, 8)).astype(np.uint8)
+    ones_a = np.ones_like(A)
+    ones_b = np.ones_like(B)
+    r = oracle.align(A, ones_a, B, ones_b, 1, 3, [0.0, 0.4, math.pi], 0.5,
+                     per_angle=True)
+    assert (r["angle_index"], r["dy"], r["dx"], r["mi"]) == (-1, 0, 0, 0.0)
+    # every angle had an eligible pick, with MI exactly 0
+    assert all(p["mi"] == 0.0 and p["n"] > 0 for p in r["per_angle"])
+    # one positive angle among non-positive ones is taken
+    A2 = rng.integers(0, 2, size=(9, 11)).astype(np.uint8)
+    r2 = oracle.align(A2, ones_a, B, ones_b, 2, 3, [0.0, 0.4], 0.5)
+    assert r2["angle_index"] in (0, 1) and r2["mi"] > 0.0
+
+
+def test_mi_of_joint_vs_sklearn_contingency(oracle):
+    """Eq. 2 / Eq. 12 on an explicit joint table against scikit-learn's MI
+    of the same contingency table (nats, divided by ln 2), including empty
+    rows and columns (0 log 0 = 0) and the all-zero table (MI = 0)."""
+    rng = np.random.default_rng(17)
+    for qa, qb in ((2, 2), (3, 5), (7, 4), (16, 16)):
+        for _ in range(5):
+            t = rng.integers(0, 40, size=(qa, qb)).astype(np.int64)
+            t[rng.integers(0, qa)] = 0          # an empty row of A
+            ref = mutual_info_score(None, None, contingency=t) / math.log(2.0)
+            assert abs(oracle.mi_of_joint(t.astype(np.float64)) - ref) <= 1e-12
+    assert oracle.mi_of_joint(np.zeros((3, 3))) == 0.0
+    # independent table: p_ab = p_a p_b exactly gives MI = 0
+    ind = np.outer([1, 2, 3], [4, 4, 8]).astype(np.float64)
+    assert abs(oracle.mi_of_joint(ind)) <= 1e-15
+
+
 # -- digest: Vigna's splitmix64 reference outputs ------------------------------
 
 def test_digest_weight_reference_values(oracle):
