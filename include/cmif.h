@@ -306,6 +306,26 @@ cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
                           size_t persistent_bytes, void* scratch,
                           size_t scratch_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   cmif_compute with both workspaces placed in a library-owned device array
+   of CMIF_NOALLOC_BYTES per GPU instead of caller buffers.  The caller
+   still passes inputs and outputs exactly as for cmif_compute, and the
+   results are the same.  The call allocates nothing: the array is a
+   file-scope device variable that each GPU the library runs on holds from
+   its first such call until the process ends; it is launched eagerly (no
+   graph capture, no launch-shape tuning, no stage profiling).  Every call
+   on one GPU shares that GPU's array and the array keeps the last call's
+   contents (each call rebuilds its tables and clears its counters before
+   use), so calls whose execution overlaps on one GPU race: order them on
+   one stream or synchronise.  Errors: as cmif_compute, plus
+   CMIF_ERR_UNSUPPORTED when the plan's persistent plus scratch workspace
+   (256-byte rounded) exceeds CMIF_NOALLOC_BYTES or the plan is SOFT with
+   CMIF_FLAG_SAVE_FOR_BACKWARD (no state is kept for cmif_backward). */
+#define CMIF_NOALLOC_BYTES ((size_t)128 << 20)
+cmif_status cmif_compute_noalloc(cmif_plan_t plan, const cmif_inputs* in,
+                                 const cmif_outputs* out, void* stream);
+
 /* Stage timing (a tracing aid).  While enabled on a plan, every kernel that
    a call enqueues is bracketed by two hipEvents recorded on the call's
    stream; cmif_profile_read waits for the recorded events and returns, per

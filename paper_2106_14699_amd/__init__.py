@@ -43,7 +43,9 @@ CMIF_FLAG_AUTOTUNE = 1 << 4
 EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_compute", "cmif_align", "cmif_backward",
             "cmif_profile_enable", "cmif_profile_read", "cmif_plan_query",
-            "cmif_status_string", "cmif_last_error", "cmif_kmeans")
+            "cmif_status_string", "cmif_last_error", "cmif_kmeans",
+            "cmif_compute_noalloc")
+NOALLOC_BYTES = 128 << 20  # CMIF_NOALLOC_BYTES
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
@@ -156,6 +158,9 @@ def _load_lib():
     lib.cmif_align.argtypes = [_P, ctypes.POINTER(cmif_inputs), _P, _P, _P, _P,
                                S, _P, S, _P]
     lib.cmif_align.restype = ctypes.c_int
+    lib.cmif_compute_noalloc.argtypes = [_P, ctypes.POINTER(cmif_inputs),
+                                         ctypes.POINTER(cmif_outputs), _P]
+    lib.cmif_compute_noalloc.restype = ctypes.c_int
     lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
                                   _PP, _P, S, _P, S, _P]
     lib.cmif_backward.restype = ctypes.c_int
@@ -220,6 +225,12 @@ def cmif_compute(plan, inputs, outputs, persistent, persistent_bytes, scratch,
                              ctypes.byref(outputs), _P(persistent),
                              persistent_bytes, _P(scratch), scratch_bytes,
                              _P(stream)), "cmif_compute")
+
+
+def cmif_compute_noalloc(plan, inputs, outputs, stream) -> None:
+    _check(_lib.cmif_compute_noalloc(_P(plan), ctypes.byref(inputs),
+                                     ctypes.byref(outputs), _P(stream)),
+           "cmif_compute_noalloc")
 
 
 def cmif_align(plan, inputs, best, per_angle, stats, persistent,
@@ -431,14 +442,15 @@ class Plan:
 
     def compute(self, A, MA=None, B=None, MB=None, *, mi=True, n=True,
                 counts=False, digest=False, best=False, per_angle=False,
-                reuse=False, allow_inexact=False):
+                reuse=False, allow_inexact=False, noalloc=False):
         """CMIF maps for every pair and angle.  Returns a dict of lists (one
         entry per pair) of torch tensors, plus 'stats' (dict).  With
         reuse=True the output tensors belong to the plan and are overwritten
         by its next call (stable pointers replay the captured graph).
         Raises CmifInexactError when flagged label pairs were left without
         their FP64 re-run (stats['unresolved_pairs'] > 0), unless
-        allow_inexact=True."""
+        allow_inexact=True.  noalloc=True calls cmif_compute_noalloc (the
+        library's own workspace array) instead of cmif_compute."""
         torch = self._torch
         inp, keep = self._inputs(A, MA, B, MB)
         na = len(self.angles)
@@ -470,9 +482,12 @@ class Plan:
         outs.best = best_t.data_ptr() if best else None
         outs.per_angle = pa_t.data_ptr() if per_angle else None
         outs.stats = stats_t.data_ptr()
-        pb, pp, sb, sp = self.workspace()
-        cmif_compute(self.handle, inp, outs, pp, self.persistent_bytes, sp,
-                     self.scratch_bytes, self._stream())
+        if noalloc:
+            cmif_compute_noalloc(self.handle, inp, outs, self._stream())
+        else:
+            pb, pp, sb, sp = self.workspace()
+            cmif_compute(self.handle, inp, outs, pp, self.persistent_bytes, sp,
+                         self.scratch_bytes, self._stream())
         torch.cuda.current_stream(self.device).synchronize()
         res["stats"] = _stats_dict(stats_t)
         if best:

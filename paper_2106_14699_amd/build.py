@@ -22,7 +22,8 @@ ARCH = "gfx950"
 
 # (source, object name, defines): the row kernels are compiled once per
 # (precision, FFT length) so that the build runs in parallel
-SOURCES = [("api.cpp", "api", []), ("k_forward.hip", "k_forward", []),
+SOURCES = [("api.cpp", "api", []), ("noalloc.hip", "noalloc", []),
+           ("k_forward.hip", "k_forward", []),
            ("k_pair.hip", "k_pair", []), ("k_misc.hip", "k_misc", []),
            ("k_soft.hip", "k_soft_f32", ["-DCMIF_SOFT_T=float"]),
            ("k_soft.hip", "k_soft_f64", ["-DCMIF_SOFT_T=double"]),

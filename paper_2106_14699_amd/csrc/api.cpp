@@ -1194,6 +1194,42 @@ cmif_status run_graph(cmif_plan_s* P, int op, std::vector<uintptr_t> key,
 
 }  // namespace
 
+namespace cmif {
+
+cmif_status set_error(cmif_status s, const char* msg) { return fail(s, msg); }
+
+cmif_status plan_noalloc_info(cmif_plan_t plan, int* device, size_t* persistent,
+                              size_t* scratch, uint32_t* flags, int32_t* mode) {
+  if (!plan) return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan");
+  *device = plan->d.device;
+  *persistent = plan->persistent_bytes;
+  *scratch = plan->scratch_bytes;
+  *flags = plan->d.flags;
+  *mode = plan->d.mode;
+  return CMIF_OK;
+}
+
+cmif_status compute_eager(cmif_plan_t plan, const cmif_inputs* in,
+                          const cmif_outputs* out, void* persistent,
+                          void* scratch, hipStream_t st) {
+  cmif_status s = check_inputs(plan, in);
+  if (s != CMIF_OK) return s;
+  s = check_device(plan);
+  if (s != CMIF_OK) return s;
+  DeviceGuard dg(plan->d.device);
+  if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
+  // the stage profiler records events: off for this call
+  const bool prof = plan->prof.on;
+  plan->prof.on = false;
+  s = run_calls(plan, in, out, out ? out->best : nullptr,
+                out ? out->per_angle : nullptr, out ? out->stats : nullptr,
+                persistent, scratch, st);
+  plan->prof.on = prof;
+  return s;
+}
+
+}  // namespace cmif
+
 extern "C" {
 
 const char* cmif_status_string(cmif_status s) {

@@ -320,6 +320,18 @@ struct PlainEntropyArgs {
 hipError_t launch_plain_entropy(const PlainEntropyArgs& a, hipStream_t st);
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
 
+// Host-side hooks of the plan object for the allocation-free entry point
+// (noalloc.hip): the plan's device and workspace sizes, and one eager
+// cmif_compute pass on caller-placed workspaces (no graph capture, no
+// tuning, no stage profiling: nothing that creates runtime objects).
+cmif_status plan_noalloc_info(cmif_plan_t plan, int* device,
+                              size_t* persistent, size_t* scratch,
+                              uint32_t* flags, int32_t* mode);
+cmif_status compute_eager(cmif_plan_t plan, const cmif_inputs* in,
+                          const cmif_outputs* out, void* persistent,
+                          void* scratch, hipStream_t st);
+cmif_status set_error(cmif_status s, const char* msg);
+
 // Mini-batch k-means quantisation (k_kmeans.hip).
 struct KmeansArgs {
   const float* img;         // [n][m] pixels x channels
