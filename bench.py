@@ -304,7 +304,10 @@ def table1_context(cm, torch, np, synth, dev):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         b = r["best"]
+        cerr = cm.cmif_corner_error(b, (n, n, n, n), c["truth"])
         out.append(dict(image=[n, n], k=16, angles="200+32", wall_s=round(wall, 3),
+                        corner_error_px=round(cerr, 3),
+                        success=bool(cerr < 0.02 * n),
                         paper_s=PAPER_TABLE1_S[n],
                         paper_over_ours=round(PAPER_TABLE1_S[n] / wall, 1),
                         best=dict(angle_deg=round(math.degrees(b["angle_rad"]), 3),
@@ -642,6 +645,10 @@ def main():
                    for s in stages},
         "best": dict(angle_deg=round(math.degrees(best["angle_rad"]), 3),
                      dy=best["dy"], dx=best["dx"], mi=best["mi"], n=best["n"],
+                     corner_error_px=round(cm.cmif_corner_error(
+                         best, (n, n, n, n), c["truth"]), 3),
+                     success=bool(cm.cmif_corner_error(
+                         best, (n, n, n, n), c["truth"]) < 0.02 * n),
                      truth_deg=round(c["theta_deg"], 3),
                      truth_shift=list(c["shift"])),
         "wall_s": round(wall, 3),

@@ -164,10 +164,11 @@ typedef struct cmif_plan_desc {
                                 pair.  Maps, counts, digests, N, the gamma
                                 threshold (gamma * max N over the window)
                                 and the argmax cover the window only, and
-                                the FFT side per axis is the smallest power
-                                of two >= max(y1 + h_a, h_b - y0) (>= 128),
-                                the least that keeps the window free of
-                                circular aliasing.  HARD mode, fused
+                                the FFT side per axis is the smallest
+                                supported length (see cmif_plan) >=
+                                max(y1 + h_a, h_b - y0), the least that
+                                keeps the window free of circular
+                                aliasing.  HARD mode, fused
                                 schedule only (otherwise
                                 CMIF_ERR_UNSUPPORTED) */
 } cmif_plan_desc;
@@ -234,9 +235,11 @@ typedef struct cmif_outputs {
   cmif_stats* stats;       /* one struct, accumulated */
 } cmif_outputs;
 
-/* Builds a plan: validates the description, chooses FFT sizes (smallest
-   power of two >= S per axis, at least 128; with a window the alias-free
-   size of the window), workspace layout and angle batching, and computes
+/* Builds a plan: validates the description, chooses FFT sizes (per axis
+   the smallest of 128, 256, 512, 768, 1024, 1536, 2048 -- lengths 2^k and
+   3 * 2^k -- that reaches S = h_a + h_b - 1, or with a window the
+   alias-free size of the window; above 2048 CMIF_ERR_UNSUPPORTED),
+   workspace layout and angle batching, and computes
    the fixed-point rotation coefficients.  Touches no device memory.  On
    success *out owns host memory released by cmif_plan_free.  Errors:
    CMIF_ERR_INVALID_ARGUMENT (NULL desc/out/size arrays, n_pairs < 1, sizes
@@ -287,6 +290,53 @@ cmif_status cmif_align(cmif_plan_t plan, const cmif_inputs* in,
                        cmif_stats* stats, void* persistent,
                        size_t persistent_bytes, void* scratch,
                        size_t scratch_bytes, void* stream);
+
+/* Global rigid alignment run twice (Sec. 3.6): (i) Alg. 1 over the plan's
+   angles (the grid Omega), then (ii) for each image pair p Alg. 1 over the
+   n_refine angles theta*_p + u_k * 2 pi / |Omega|, k < n_refine, around the
+   grid's best angle theta*_p (0 when the grid kept the identity), with
+   u_k = refine_offsets[k] in [-1, 1] (host array; the paper samples the
+   interval uniformly at random, so the caller draws the u_k).  Across the
+   stages a refinement result replaces the grid's only with a strictly
+   larger MI (the refinement angles follow the grid in Alg. 1's order).
+   HARD plans only.  best (device, [n_pairs]) receives the final result:
+   angle_index < n_angles is a grid angle, n_angles + k the k-th refinement
+   angle, -1 the identity; grid_best and refine_best (device, [n_pairs],
+   nullable) receive the two stage results (refine_best's angle_index
+   indexes the refinement angles).  stats (nullable) accumulates both
+   stages.  The same workspaces as cmif_align.  Unlike the other calls this
+   one waits for stage (i) on `stream` before it enqueues stage (ii), whose
+   angles depend on theta*; results are valid once the stream has been
+   synchronised.  Errors: as cmif_align, CMIF_ERR_WRONG_MODE for SOFT
+   plans, CMIF_ERR_INVALID_ARGUMENT for n_refine outside 1..4096, NULL or
+   out-of-range offsets. */
+cmif_status cmif_align_two_stage(cmif_plan_t plan, const cmif_inputs* in,
+                                 int32_t n_refine, const double* refine_offsets,
+                                 cmif_best* best, cmif_best* grid_best,
+                                 cmif_best* refine_best, cmif_stats* stats,
+                                 void* persistent, size_t persistent_bytes,
+                                 void* scratch, size_t scratch_bytes,
+                                 void* stream);
+
+/* The success measure of the paper's alignment experiments (Sec. 5.2): the
+   mean Euclidean distance, in reference-image pixels, between the four
+   corners of the reference image A taken as landmarks and the positions the
+   alignment result recovers for them, against a known true transform.  An
+   alignment counts as successful when this is below 2 % of the image
+   width.  result (host) is an Alg. 1 result for images of sides h_a x w_a
+   (A) and h_b x w_b (B); its correspondence maps A's pixel x to B's pixel
+   R(theta)(x + chi - c_B) + c_B (the identity for angle_index -1), with
+   c_B = ((w_b - 1)/2, (h_b - 1)/2) and R(theta) the rotation of cmif_plan's
+   resampling rule in exact arithmetic.  truth (host, 6 doubles) is the true
+   correspondence as an affine map of A's pixel (x, y) to B's:
+   (truth[0] x + truth[1] y + truth[2], truth[3] x + truth[4] y + truth[5]).
+   Both maps are rigid, so distances between the mapped corners in B equal
+   those between the recovered and the true landmark positions in A.  Writes
+   the mean distance to *error_px.  Host only, no device work.  Errors:
+   CMIF_ERR_INVALID_ARGUMENT (NULL pointers, sides < 1). */
+cmif_status cmif_corner_error(const cmif_best* result, int32_t h_a, int32_t w_a,
+                              int32_t h_b, int32_t w_b, const double* truth,
+                              double* error_px);
 
 /* SOFT plans with CMIF_FLAG_SAVE_FOR_BACKWARD (which cmif_plan accepts for
    the single angle 0 only), after cmif_compute on the same inputs: given

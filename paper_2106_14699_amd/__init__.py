@@ -44,7 +44,8 @@ EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_compute", "cmif_align", "cmif_backward",
             "cmif_profile_enable", "cmif_profile_read", "cmif_plan_query",
             "cmif_status_string", "cmif_last_error", "cmif_kmeans",
-            "cmif_compute_noalloc")
+            "cmif_compute_noalloc", "cmif_align_two_stage",
+            "cmif_corner_error")
 NOALLOC_BYTES = 128 << 20  # CMIF_NOALLOC_BYTES
 
 _P = ctypes.c_void_p
@@ -161,6 +162,17 @@ def _load_lib():
     lib.cmif_compute_noalloc.argtypes = [_P, ctypes.POINTER(cmif_inputs),
                                          ctypes.POINTER(cmif_outputs), _P]
     lib.cmif_compute_noalloc.restype = ctypes.c_int
+    lib.cmif_align_two_stage.argtypes = [_P, ctypes.POINTER(cmif_inputs),
+                                         ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_double), _P,
+                                         _P, _P, _P, _P, S, _P, S, _P]
+    lib.cmif_align_two_stage.restype = ctypes.c_int
+    lib.cmif_corner_error.argtypes = [ctypes.POINTER(cmif_best), ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.cmif_corner_error.restype = ctypes.c_int
     lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
                                   _PP, _P, S, _P, S, _P]
     lib.cmif_backward.restype = ctypes.c_int
@@ -239,6 +251,36 @@ def cmif_align(plan, inputs, best, per_angle, stats, persistent,
                            _P(per_angle), _P(stats), _P(persistent),
                            persistent_bytes, _P(scratch), scratch_bytes,
                            _P(stream)), "cmif_align")
+
+
+def cmif_align_two_stage(plan, inputs, n_refine, refine_offsets, best,
+                         grid_best, refine_best, stats, persistent,
+                         persistent_bytes, scratch, scratch_bytes,
+                         stream) -> None:
+    _check(_lib.cmif_align_two_stage(_P(plan), ctypes.byref(inputs),
+                                     int(n_refine), refine_offsets, _P(best),
+                                     _P(grid_best), _P(refine_best), _P(stats),
+                                     _P(persistent), persistent_bytes,
+                                     _P(scratch), scratch_bytes, _P(stream)),
+           "cmif_align_two_stage")
+
+
+def cmif_corner_error(result: dict, sizes, truth) -> float:
+    """Mean corner (landmark) error in reference pixels of an Alg. 1
+    result dict (best_from_bytes) for image sides (h_a, w_a, h_b, w_b)
+    against the true A -> B affine map truth (6 numbers)."""
+    b = cmif_best()
+    b.angle_index = int(result["angle_index"])
+    b.dy, b.dx = int(result["dy"]), int(result["dx"])
+    b.angle_rad = float(result["angle_rad"])
+    b.mi = float(result.get("mi", 0.0))
+    b.n = int(result.get("n", 0))
+    t = (ctypes.c_double * 6)(*[float(v) for v in truth])
+    e = ctypes.c_double()
+    ha, wa, hb, wb = (int(v) for v in sizes)
+    _check(_lib.cmif_corner_error(ctypes.byref(b), ha, wa, hb, wb, t,
+                                  ctypes.byref(e)), "cmif_corner_error")
+    return e.value
 
 
 def cmif_backward(plan, inputs, grad_mi, grad_a, grad_b, persistent,
@@ -550,6 +592,42 @@ class Plan:
         return res
 
 
+def _plan_align_two_stage(self, A, MA=None, B=None, MB=None, *,
+                          refine_offsets, allow_inexact=False):
+    """Sec. 3.6's two-stage alignment through cmif_align_two_stage: Alg. 1
+    over the plan's angles, then per pair over theta* + u_k 2 pi / |angles|
+    for the given offsets u_k in [-1, 1].  Returns dict(best, grid_best,
+    refine_best: lists per pair, stats)."""
+    torch = self._torch
+    inp, keep = self._inputs(A, MA, B, MB)
+    u = [float(v) for v in refine_offsets]
+    uarr = (ctypes.c_double * len(u))(*u)
+    n = len(self.sizes)
+    nbest = ctypes.sizeof(cmif_best)
+    bufs = [self._buffer(True, ("t", k), (n, nbest), torch.uint8)
+            for k in ("best", "grid", "refine")]
+    stats_t = self._buffer(True, ("t", "stats"), (ctypes.sizeof(cmif_stats),),
+                           torch.uint8)
+    stats_t.zero_()
+    pb, pp, sb, sp = self.workspace()
+    cmif_align_two_stage(self.handle, inp, len(u), uarr, bufs[0].data_ptr(),
+                         bufs[1].data_ptr(), bufs[2].data_ptr(),
+                         stats_t.data_ptr(), pp, self.persistent_bytes, sp,
+                         self.scratch_bytes, self._stream())
+    torch.cuda.current_stream(self.device).synchronize()
+    del keep
+    out = [[best_from_bytes(bytes(t[p].cpu().numpy())) for p in range(n)]
+           for t in bufs]
+    res = dict(best=out[0], grid_best=out[1], refine_best=out[2],
+               stats=_stats_dict(stats_t))
+    if res["stats"]["unresolved_pairs"] and not allow_inexact:
+        raise CmifInexactError("cmif_align_two_stage", res["stats"], res)
+    return res
+
+
+Plan.align_two_stage = _plan_align_two_stage
+
+
 def stats_from_raw(stats_t) -> dict:
     """cmif_stats (a device or host uint8 tensor of its bytes) as a dict."""
     return _stats_dict(stats_t)
@@ -611,39 +689,33 @@ def kmeans_quantize(image, k, *, iters=25, batch=1000, rng=None, mask=None,
 
 
 def align_two_stage(A, MA, B, MB, size, q_a, q_b, grid, *, n_refine=32,
-                    rng=None, refine_angles=None, gamma=0.5, precision="fp32",
+                    rng=None, refine_offsets=None, gamma=0.5, precision="fp32",
                     flags=0, window=None, device=0):
-    """Global rigid alignment run twice (Sec. 3.6): Alg. 1 over the grid of
-    angles `grid`, then over n_refine angles drawn uniformly from
+    """Global rigid alignment run twice (Sec. 3.6) for one image pair of
+    sides `size` = (h_a, w_a, h_b, w_b): one cmif_align_two_stage call, Alg.
+    1 over the angles `grid`, then over n_refine angles drawn uniformly from
     [theta* - 2 pi/|grid|, theta* + 2 pi/|grid|] around the grid's best
-    angle theta*.  A refinement result replaces the grid's only with a
-    strictly larger MI (the refinement angles come after the grid in Alg. 1's
-    order).  One image pair of sides `size` = (h_a, w_a, h_b, w_b).  The
-    draws come from `rng` (a numpy Generator), or the caller passes the
-    refinement angles themselves.  Both stages run through cmif_align.
-    Returns dict(best, stage ('grid' or 'refine'), grid_best, refine_best,
-    refine_angles)."""
+    angle theta*.  The draws are offsets u_k uniform in [-1, 1] from `rng`
+    (a numpy Generator), made on the host, or the caller passes
+    refine_offsets.  Returns dict(best, stage ('grid' or 'refine'),
+    grid_best, refine_best, refine_offsets)."""
     import numpy as np
     grid = [float(t) for t in grid]
-    wins = None if window is None else [tuple(window)]
-    p1 = Plan([size], q_a, q_b, angles=grid, gamma=gamma, precision=precision,
-              flags=flags, device=device, windows=wins)
-    g = p1.align(A, MA, B, MB)["best"][0]
-    del p1
-    if refine_angles is None:
+    if refine_offsets is None:
         if rng is None:
-            raise ValueError("pass rng (numpy Generator) or refine_angles")
-        half = 2.0 * math.pi / len(grid)
-        refine_angles = rng.uniform(g["angle_rad"] - half, g["angle_rad"] + half,
-                                    int(n_refine))
-    refine_angles = [float(t) for t in np.asarray(refine_angles).ravel()]
-    p2 = Plan([size], q_a, q_b, angles=refine_angles, gamma=gamma,
-              precision=precision, flags=flags, device=device, windows=wins)
-    r = p2.align(A, MA, B, MB)["best"][0]
-    del p2
-    best, stage = (r, "refine") if r["mi"] > g["mi"] else (g, "grid")
-    return dict(best=best, stage=stage, grid_best=g, refine_best=r,
-                refine_angles=refine_angles)
+            raise ValueError("pass rng (numpy Generator) or refine_offsets")
+        refine_offsets = rng.uniform(-1.0, 1.0, int(n_refine))
+    u = [float(v) for v in np.asarray(refine_offsets).ravel()]
+    wins = None if window is None else [tuple(window)]
+    plan = Plan([size], q_a, q_b, angles=grid, gamma=gamma, precision=precision,
+                flags=flags, device=device, windows=wins)
+    r = plan.align_two_stage(A, MA, B, MB, refine_offsets=u)
+    del plan
+    best = r["best"][0]
+    return dict(best=best,
+                stage="refine" if best["angle_index"] >= len(grid) else "grid",
+                grid_best=r["grid_best"][0], refine_best=r["refine_best"][0],
+                refine_offsets=u)
 
 
 def _plan_backward(self, A, MA, B, MB, grad_mi, *, want_a=True, want_b=True):

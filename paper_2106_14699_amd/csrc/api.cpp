@@ -41,10 +41,12 @@ cmif_status fail(cmif_status s, const std::string& msg) {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int pow2_at_least(int v) {
-  int p = kMinP;
-  while (p < v) p <<= 1;
-  return p;
+// FFT side: the smallest compiled length (2^k or 3 * 2^k, >= 128) that
+// reaches v, or 0 when none does
+int fft_size_at_least(int v) {
+  for (int p : kFftSizes)
+    if (p >= v) return p;
+  return 0;
 }
 
 // Geometry of one image pair: image sides, map size (the displacement
@@ -140,6 +142,7 @@ struct cmif_plan_s {
   size_t scratch_bytes = 0;
   int nchunks_max = 1;
   bool device_checked = false;
+  bool windowed = false;        // built with per-pair displacement windows
   Profiler prof;
   GraphCache graphs[2];  // [0] cmif_compute, [1] cmif_align
   int graph_captures = 0;
@@ -1354,6 +1357,7 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   P->d.h_a = P->d.w_a = P->d.h_b = P->d.w_b = nullptr;
   P->d.angles_rad = nullptr;
   P->d.window = nullptr;
+  P->windowed = d->window != nullptr;
   if (d->tune_cache_path) P->tune_path = d->tune_cache_path;
   P->d.tune_cache_path = nullptr;
   for (int p = 0; p < d->n_pairs; ++p) {
@@ -1381,9 +1385,9 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
     g.eha = 1 - y0; g.ehb = y1 + 1; g.ewa = 1 - x0; g.ewb = x1 + 1;
     g.sh = y1 - y0 + 1;
     g.sw = x1 - x0 + 1;
-    g.ph = pow2_at_least(std::max(y1 + g.ha, g.hb - y0));
-    g.pw = pow2_at_least(std::max(x1 + g.wa, g.wb - x0));
-    if (g.ph > kMaxP || g.pw > kMaxP) {
+    g.ph = fft_size_at_least(std::max(y1 + g.ha, g.hb - y0));
+    g.pw = fft_size_at_least(std::max(x1 + g.wa, g.wb - x0));
+    if (g.ph == 0 || g.pw == 0) {
       delete P;
       return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 2048");
     }
@@ -1595,6 +1599,108 @@ cmif_status cmif_backward(cmif_plan_t plan, const cmif_inputs* in,
                                    grad_mi[p], ga, gb, pb, sb, st);
     if (s != CMIF_OK) return s;
   }
+  return CMIF_OK;
+}
+
+cmif_status cmif_align_two_stage(cmif_plan_t plan, const cmif_inputs* in,
+                                 int32_t n_refine, const double* refine_offsets,
+                                 cmif_best* best, cmif_best* grid_best,
+                                 cmif_best* refine_best, cmif_stats* stats,
+                                 void* persistent, size_t persistent_bytes,
+                                 void* scratch, size_t scratch_bytes,
+                                 void* stream) {
+  g_err.clear();
+  if (!plan || !in || !best)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL plan, inputs or best");
+  if (plan->d.mode != CMIF_MODE_HARD)
+    return fail(CMIF_ERR_WRONG_MODE, "the two-stage alignment takes HARD plans");
+  if (n_refine < 1 || n_refine > 4096 || refine_offsets == nullptr)
+    return fail(CMIF_ERR_INVALID_ARGUMENT,
+                "n_refine must be in [1, 4096] with its offsets given");
+  for (int k = 0; k < n_refine; ++k)
+    if (!(std::fabs(refine_offsets[k]) <= 1.0))
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "refinement offsets must lie in [-1, 1]");
+  cmif_status s = check_inputs(plan, in);
+  if (s != CMIF_OK) return s;
+  // stage (i): Alg. 1 over the plan's angle grid, into best
+  s = cmif_align(plan, in, best, nullptr, stats, persistent, persistent_bytes,
+                 scratch, scratch_bytes, stream);
+  if (s != CMIF_OK) return s;
+  DeviceGuard dg(plan->d.device);
+  if (!dg.ok) return fail(CMIF_ERR_DEVICE, "cannot select the plan's device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int np = plan->d.n_pairs;
+  std::vector<cmif_best> grid((size_t)np);
+  HIP_TRY(hipMemcpyAsync(grid.data(), best, np * sizeof(cmif_best),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  // stage (ii), per image pair: Alg. 1 over theta* + u_k 2 pi / |Omega|
+  const double half = 2.0 * M_PI / (double)plan->angles.size();
+  std::vector<double> ang((size_t)n_refine);
+  for (int p = 0; p < np; ++p) {
+    const PairPlan& g = plan->pairs[p];
+    const double th0 = grid[p].angle_index >= 0 ? grid[p].angle_rad : 0.0;
+    for (int k = 0; k < n_refine; ++k) ang[k] = th0 + refine_offsets[k] * half;
+    cmif_plan_desc d = plan->d;
+    d.n_pairs = 1;
+    d.h_a = &g.ha; d.w_a = &g.wa; d.h_b = &g.hb; d.w_b = &g.wb;
+    d.n_angles = n_refine;
+    d.angles_rad = ang.data();
+    d.flags = (plan->d.flags & ~(uint32_t)CMIF_FLAG_AUTOTUNE) | CMIF_FLAG_NO_GRAPH;
+    // no more angles per pass than the grid plan: the workspace it was
+    // given then fits this plan too
+    d.angle_batch = plan->batch;
+    d.tune_cache_path = nullptr;
+    const int32_t win[4] = {1 - g.eha, g.ehb - 1, 1 - g.ewa, g.ewb - 1};
+    d.window = plan->windowed ? win : nullptr;
+    cmif_plan_t p2 = nullptr;
+    s = cmif_plan(&d, &p2);
+    if (s != CMIF_OK) return s;
+    p2->rows_per_wg = plan->rows_per_wg;
+    p2->bpw = plan->bpw;
+    p2->xcd = plan->xcd;
+    const uint8_t* la = in->labels_a[p];
+    const uint8_t* lb = in->labels_b[p];
+    const uint8_t* ma = in->mask_a ? in->mask_a[p] : nullptr;
+    const uint8_t* mb = in->mask_b ? in->mask_b[p] : nullptr;
+    cmif_inputs one{};
+    one.labels_a = &la; one.labels_b = &lb; one.mask_a = &ma; one.mask_b = &mb;
+    s = cmif_align(p2, &one, best + p, nullptr, stats, persistent,
+                   persistent_bytes, scratch, scratch_bytes, stream);
+    cmif_plan_free(p2);
+    if (s != CMIF_OK) return s;
+    HIP_TRY(launch_two_stage_combine(grid[p], best + p,
+                                     grid_best ? grid_best + p : nullptr,
+                                     refine_best ? refine_best + p : nullptr,
+                                     (int)plan->angles.size(), st));
+  }
+  return CMIF_OK;
+}
+
+cmif_status cmif_corner_error(const cmif_best* result, int32_t h_a, int32_t w_a,
+                              int32_t h_b, int32_t w_b, const double* truth,
+                              double* error_px) {
+  g_err.clear();
+  if (!result || !truth || !error_px)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (h_a < 1 || w_a < 1 || h_b < 1 || w_b < 1)
+    return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be >= 1");
+  // the result's correspondence A -> B: x -> R(theta)(x + chi - c_B) + c_B
+  // (the identity when Alg. 1 kept it)
+  const double th = result->angle_index >= 0 ? result->angle_rad : 0.0;
+  const double ct = std::cos(th), sn = std::sin(th);
+  const double cx = 0.5 * (w_b - 1), cy = 0.5 * (h_b - 1);
+  const double cxs[4] = {0.0, (double)(w_a - 1), 0.0, (double)(w_a - 1)};
+  const double cys[4] = {0.0, 0.0, (double)(h_a - 1), (double)(h_a - 1)};
+  double sum = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const double vx = cxs[k] + result->dx - cx, vy = cys[k] + result->dy - cy;
+    const double rx = ct * vx - sn * vy + cx, ry = sn * vx + ct * vy + cy;
+    const double tx = truth[0] * cxs[k] + truth[1] * cys[k] + truth[2];
+    const double ty = truth[3] * cxs[k] + truth[4] * cys[k] + truth[5];
+    sum += std::hypot(rx - tx, ry - ty);
+  }
+  *error_px = 0.25 * sum;
   return CMIF_OK;
 }
 

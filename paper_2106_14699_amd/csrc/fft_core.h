@@ -11,12 +11,15 @@
 // above, the reads of every stage are exactly the lane's own registers, and
 // the last stage lands in natural order without an exchange.
 //
-// Radices are chosen greedily, r = min(16, R, N/Ns) (R = N/TEAM points per
-// lane), e.g. N = 1024 over 128 lanes runs as 8 x 8 x 8 x 2 with three LDS
-// exchanges.  Twiddles come from a table tw[t] = exp(+2 pi i t / N) computed
-// in FP64 (no recurrences); each lane keeps the entries it needs in
-// registers; DIR = -1 (forward) uses their conjugates.  Transforms are
-// unnormalised both ways.
+// Lengths are 2^k or 3 * 2^k.  Radices are chosen greedily: the largest r in
+// {16, 12, 8, 4, 3, 2} that divides both R = N/TEAM (points per lane) and
+// the length still to be split, N/Ns; e.g. N = 1024 over 128 lanes runs as
+// 8 x 8 x 8 x 2 with three LDS exchanges, N = 768 over 64 lanes as
+// 12 x 4 x 4 x 4 (the stage formula above holds for any sequence of
+// radices, with Ns the product of the radices before the stage).  Twiddles
+// come from a table tw[t] = exp(+2 pi i t / N) computed in FP64 (no
+// recurrences); each lane keeps the entries it needs in registers; DIR = -1
+// (forward) uses their conjugates.  Transforms are unnormalised both ways.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -117,11 +120,66 @@ __device__ __forceinline__ void dft16(C2<T>* a) {
   }
 }
 
+// DFT of length 3: with w = exp(S 2 pi i / 3) = -1/2 + S i sqrt(3)/2,
+// X1,2 = x0 - (x1 + x2)/2 +- S i (sqrt(3)/2)(x1 - x2).
+template <typename T, int S>
+__device__ __forceinline__ void dft3(C2<T>& a0, C2<T>& a1, C2<T>& a2) {
+  const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+  const C2<T> t1 = cadd<T>(a1, a2), t2 = csub<T>(a1, a2);
+  const C2<T> m = mk<T>(a0.x - (T)0.5 * t1.x, a0.y - (T)0.5 * t1.y);
+  const C2<T> r = mul_si<T, S>(cscale<T>(t2, h));
+  a0 = cadd<T>(a0, t1);
+  a1 = cadd<T>(m, r);
+  a2 = csub<T>(m, r);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft3a(C2<T>* a) { dft3<T, S>(a[0], a[1], a[2]); }
+
+// DFT of length 12 as 3 x 4 (Cooley-Tukey, n = 4 n1 + n2, k = k1 + 3 k2):
+// four length-3 DFTs over n1, twiddles w12^(n2 k1), three length-4 DFTs
+// over n2.
+template <typename T, int S>
+__device__ __forceinline__ void dft12(C2<T>* a) {
+  C2<T> y[4][3];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = a[n2];
+    y[n2][1] = a[4 + n2];
+    y[n2][2] = a[8 + n2];
+    dft3<T, S>(y[n2][0], y[n2][1], y[n2][2]);
+  }
+  // w12^e = (cos(pi e / 6), S sin(pi e / 6)) for e = n2 k1 in 1..6
+  const T c1 = (T)0.86602540378443864676, s1 = (T)0.5;
+  const T wr[7] = {(T)1, c1, s1, (T)0, -s1, -c1, (T)-1};
+  const T wi[7] = {(T)0, s1, c1, (T)1, c1, s1, (T)0};
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < 3; ++k1) {
+      const int e = n2 * k1;
+      if (e == 3) y[n2][k1] = mul_si<T, S>(y[n2][k1]);
+      else if (e == 6) y[n2][k1] = mk<T>(-y[n2][k1].x, -y[n2][k1].y);
+      else y[n2][k1] = cmul<T>(mk<T>(wr[e], (T)S * wi[e]), y[n2][k1]);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    dft4<T, S>(y[0][k1], y[1][k1], y[2][k1], y[3][k1]);
+    a[k1] = y[0][k1];
+    a[k1 + 3] = y[1][k1];
+    a[k1 + 6] = y[2][k1];
+    a[k1 + 9] = y[3][k1];
+  }
+}
+
 template <typename T, int S, int RADIX>
 __device__ __forceinline__ void dft_r(C2<T>* a) {
   if constexpr (RADIX == 2) dft2<T, S>(a);
+  else if constexpr (RADIX == 3) dft3a<T, S>(a);
   else if constexpr (RADIX == 4) dft4a<T, S>(a);
   else if constexpr (RADIX == 8) dft8<T, S>(a);
+  else if constexpr (RADIX == 12) dft12<T, S>(a);
   else if constexpr (RADIX == 16) dft16<T, S>(a);
 }
 
@@ -141,13 +199,34 @@ __device__ __forceinline__ void team_sync() {
 }
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 
-// Stage plan: radix of the stage with Ns = ns, and how many twiddles one
-// lane needs for all stages (R/r butterflies x (r - 1) twiddles per stage with
-// Ns > 1).  The twiddles of a lane are the same for every transform it does,
-// so kernels load them once (fft_load_twiddles) and keep them in registers.
+// Stage plan: radix of the stage with Ns = ns (the largest supported radix
+// dividing both the points per lane and the length left to split), and how
+// many twiddles one lane needs for all stages (R/r butterflies x (r - 1)
+// twiddles per stage with Ns > 1).  The twiddles of a lane are the same for
+// every transform it does, so kernels load them once (fft_load_twiddles)
+// and keep them in registers.
 constexpr int stage_radix(int n, int team, int ns) {
-  return cmin(16, cmin(n / team, n / ns));
+  return cgcd(n / team, n / ns) % 16 == 0   ? 16
+         : cgcd(n / team, n / ns) % 12 == 0 ? 12
+         : cgcd(n / team, n / ns) % 8 == 0  ? 8
+         : cgcd(n / team, n / ns) % 4 == 0  ? 4
+         : cgcd(n / team, n / ns) % 3 == 0  ? 3
+         : cgcd(n / team, n / ns) % 2 == 0  ? 2
+                                             : 1;
+}
+
+// true when the greedy radices split n completely over a team
+constexpr bool fft_plan_ok(int n, int team, int ns = 1) {
+  return ns == n ? true
+                 : (stage_radix(n, team, ns) < 2 ? false
+                                                 : fft_plan_ok(n, team, ns * stage_radix(n, team, ns)));
+}
+
+// supported transform lengths: 2^k or 3 * 2^k
+constexpr bool fft_len_ok(int n) {
+  return n >= 2 && ((n & (n - 1)) == 0 || (n % 3 == 0 && ((n / 3) & (n / 3 - 1)) == 0));
 }
 
 constexpr int fft_tw_count_from(int n, int team, int ns) {
@@ -178,7 +257,7 @@ __device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM>& f,
   if constexpr (NS > 1) {
 #pragma unroll
     for (int t = 0; t < BPL; ++t) {
-      const int k = (lane + TEAM * t) & (NS - 1);
+      const int k = (lane + TEAM * t) % NS;
 #pragma unroll
       for (int m = 1; m < RAD; ++m)
         f.w[OFF + t * (RAD - 1) + (m - 1)] = tw[m * k * TSTRIDE * MUL];
@@ -230,7 +309,7 @@ __device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
 #pragma unroll
   for (int t = 0; t < BPL; ++t) {
     const int j = lane + TEAM * t;
-    const int k = j & (NS - 1);
+    const int k = j % NS;
     C2<T> x[RAD];
 #pragma unroll
     for (int m = 0; m < RAD; ++m) x[m] = v[t + m * BPL];
@@ -270,7 +349,8 @@ template <typename T, int N, int TEAM, int DIR, class TWS>
 __device__ __forceinline__ void team_fft(C2<T> (&v)[N / TEAM], C2<T>* lds,
                                          const TWS& f, int lane) {
   static_assert(N % TEAM == 0 && N / TEAM >= 2, "team too large for N");
-  static_assert((N & (N - 1)) == 0, "power-of-two lengths only");
+  static_assert(fft_len_ok(N), "lengths 2^k or 3 * 2^k only");
+  static_assert(fft_plan_ok(N, TEAM), "no radix split of N over this team");
   fft_stage<T, N, TEAM, DIR, 1, 0, TWS>(v, lds, f, lane);
 }
 

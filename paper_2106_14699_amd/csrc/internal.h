@@ -25,6 +25,9 @@ constexpr int kMaxBatch = 16;  // angles per pipeline pass (kernel argument)
 constexpr int kMinP = 128;
 constexpr int kXlogN = 2048;   // c log2 c tabulated for integer c < kXlogN
 constexpr int kMaxP = 2048;
+// FFT lengths with compiled kernels, ascending (the plan takes the smallest
+// one that reaches the alias-free size)
+constexpr int kFftSizes[] = {128, 256, 512, 768, 1024, 1536, 2048};
 
 struct RotArgs {
   int32_t c[kMaxBatch];  // round(cos(theta) * 2^16)
@@ -72,9 +75,16 @@ __host__ __device__ constexpr int z_tile_stride(int sh) {
 }
 __host__ __device__ constexpr int z_pair_slots(int n) { return (n + 1) & ~1; }
 
+// FFT lengths: 2^k or 3 * 2^k (radix-3 through the 12-point butterfly).
+constexpr bool is_pow2(int p) { return (p & (p - 1)) == 0; }
+
 // Lanes per FFT team: at most 8 points per lane (radix-8 stages), so a
-// 1024-point transform is spread over two waves and 2048 over four.
-constexpr int team_for(int p) { return p <= 512 ? 64 : p / 8; }
+// 1024-point transform is spread over two waves and 2048 over four; 3 * 2^k
+// lengths take 12 points per lane (a 12-point first stage), so 768 points
+// fill one wave and 1536 two.
+constexpr int team_for(int p) {
+  return is_pow2(p) ? (p <= 512 ? 64 : p / 8) : p / 12;
+}
 
 // Team size of the column kernels, whose workgroup holds one team per column
 // of a TW-wide tile: capped so that TW teams fit in 1024 lanes.
@@ -88,9 +98,13 @@ constexpr int col_team_for(int p) {
 // (16 points per lane: radix 16, 16, 4 with two LDS exchanges and wave-level
 // barriers only), P/16 lanes above, capped so that TW teams fit 1024 lanes.
 template <typename T>
+constexpr int pair_col_team_raw(int p) {
+  return is_pow2(p) ? (p <= 1024 ? 64 : p / 16) : p / 12;
+}
+template <typename T>
 constexpr int pair_col_team(int p) {
-  return (p <= 1024 ? 64 : p / 16) * tile_width<T>() <= 1024
-             ? (p <= 1024 ? 64 : p / 16)
+  return pair_col_team_raw<T>(p) * tile_width<T>() <= 1024
+             ? pair_col_team_raw<T>(p)
              : 1024 / tile_width<T>();
 }
 

@@ -123,7 +123,7 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
 #pragma unroll
     for (int q = 0; q < R / 2; ++q) {
       const int k = lane + TEAM * q;
-      vm[q] = lds[lpad((P - k) & (P - 1))];
+      vm[q] = lds[lpad(k == 0 ? 0 : P - k)];
     }
     team_sync<TEAM>();
     if (active) {
@@ -233,7 +233,9 @@ hipError_t launch_fwd_rows(int P, const FwdRowsArgs<T>& a, hipStream_t st) {
     case 128: return launch_rows_p<T, 128>(a, st);
     case 256: return launch_rows_p<T, 256>(a, st);
     case 512: return launch_rows_p<T, 512>(a, st);
+    case 768: return launch_rows_p<T, 768>(a, st);
     case 1024: return launch_rows_p<T, 1024>(a, st);
+    case 1536: return launch_rows_p<T, 1536>(a, st);
     case 2048: return launch_rows_p<T, 2048>(a, st);
   }
   return hipErrorInvalidValue;
@@ -262,7 +264,9 @@ hipError_t launch_fwd_cols(int P, const FwdColsArgs<T>& a, hipStream_t st) {
     case 128: return launch_cols_p<T, 128>(a, st);
     case 256: return launch_cols_p<T, 256>(a, st);
     case 512: return launch_cols_p<T, 512>(a, st);
+    case 768: return launch_cols_p<T, 768>(a, st);
     case 1024: return launch_cols_p<T, 1024>(a, st);
+    case 1536: return launch_cols_p<T, 1536>(a, st);
     case 2048: return launch_cols_p<T, 2048>(a, st);
   }
   return hipErrorInvalidValue;

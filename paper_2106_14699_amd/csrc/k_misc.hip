@@ -201,6 +201,35 @@ k_fb_list(const uint32_t* __restrict__ flags, int nb, int QA, int QB, int force,
   }
 }
 
+// Alg. 1 across the two stages of Sec. 3.6 for one image pair: the
+// refinement result (in *best, angle index into the refinement list)
+// replaces the grid's only with a strictly larger MI, its angle index then
+// counted after the n_grid grid angles.  Copies of both stage results go to
+// grid_out and refine_out when given.
+__global__ void k_two_stage_combine(cmif_best grid, cmif_best* __restrict__ best,
+                                    cmif_best* __restrict__ grid_out,
+                                    cmif_best* __restrict__ refine_out,
+                                    int n_grid) {
+  if (threadIdx.x != 0) return;
+  cmif_best r = *best;
+  if (refine_out) *refine_out = r;
+  if (grid_out) *grid_out = grid;
+  if (r.mi > grid.mi) {
+    r.angle_index = n_grid + r.angle_index;
+    *best = r;
+  } else {
+    *best = grid;
+  }
+}
+
+hipError_t launch_two_stage_combine(const cmif_best& grid, cmif_best* best,
+                                    cmif_best* grid_out, cmif_best* refine_out,
+                                    int n_grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_two_stage_combine, dim3(1), dim3(64), 0, st, grid, best,
+                     grid_out, refine_out, n_grid);
+  return hipGetLastError();
+}
+
 hipError_t launch_fb_list(const FbListArgs& a, hipStream_t st) {
   if (a.nb < 1 || a.nb > kMaxBatch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fb_list, dim3(1), dim3(1024), 0, st, a.flags, a.nb, a.QA,
@@ -224,7 +253,7 @@ __global__ void k_plain_product(const double2* __restrict__ fa,
     y[e] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
     return;
   }
-  const int km = (ph - k) & (ph - 1);
+  const int km = k == 0 ? 0 : ph - k;
   const double2 am = fa[km], bm = fb[km];
   // separate W = G0 + i G1 (G0, G1 Hermitian): G0 = (W + conj(Wm))/2,
   // G1 = (W - conj(Wm))/(2i)

@@ -165,7 +165,7 @@ __device__ __forceinline__ void pair_cols_run(
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int k = lane + TEAM * q;
-        const int km = (P - k) & (P - 1);
+        const int km = k == 0 ? 0 : P - k;
         C2<T> ga0, ga1, gb0, gb1;
         unpack0<T>(fa[q], fa_col[km], ga0, ga1);
         unpack0<T>(fb_col[k], fb_col[km], gb0, gb1);
@@ -282,7 +282,9 @@ hipError_t launch_pair_cols(int P, const PairColsArgs<T>& a, hipStream_t st) {
     case 128: return launch_pc_p<T, 128>(a, st);
     case 256: return launch_pc_p<T, 256>(a, st);
     case 512: return launch_pc_p<T, 512>(a, st);
+    case 768: return launch_pc_p<T, 768>(a, st);
     case 1024: return launch_pc_p<T, 1024>(a, st);
+    case 1536: return launch_pc_p<T, 1536>(a, st);
     case 2048: return launch_pc_p<T, 2048>(a, st);
   }
   return hipErrorInvalidValue;

@@ -292,7 +292,11 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 // Lanes of the count kernel's workgroup: up to four teams, at most 512 lanes
 // (two waves per SIMD keep 256 registers per lane; at 1024 lanes the
 // 2048-point kernel spilled; team_for gives at most 256 lanes, a divisor of 512).
-constexpr int counts_lanes(int team) { return 4 * team <= 512 ? 4 * team : 512; }
+// 3 * 2^k lengths (12 points per lane) keep two teams: with 512 lanes the
+// 1536-point kernel spilled.
+constexpr int counts_lanes(int team, int p) {
+  return !is_pow2(p) ? 2 * team : (4 * team <= 512 ? 4 * team : 512);
+}
 
 // Count emission: workgroup (map row, angle); each team takes label pairs
 // two at a time (a-major order) and writes rint(count) to
@@ -300,7 +304,7 @@ constexpr int counts_lanes(int team) { return 4 * team <= 512 ? 4 * team : 512; 
 // into digest[beta][pair] (64-bit wrap-around, order-free).  In item mode
 // the slots of Z are list items (angle, a, b) and the grid has one angle.
 template <typename T, int P, int TEAM>
-__global__ void __launch_bounds__(counts_lanes(TEAM))
+__global__ void __launch_bounds__(counts_lanes(TEAM, P))
 k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
               long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
               int sw, int ph, const C2<T>* __restrict__ tw,
@@ -450,7 +454,7 @@ template <typename T, int P>
 hipError_t launch_pair_counts_p(const PairCountsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = team_for(P);
   const size_t per_team = (size_t)lds_elems(P) * sizeof(C2<T>);
-  int nteams = counts_lanes(TEAM) / TEAM;
+  int nteams = counts_lanes(TEAM, P) / TEAM;
   while (nteams > 1 && per_team * nteams > 64 * 1024) --nteams;
   const size_t shm = per_team * nteams;
   auto fn = k_pair_counts<T, P, TEAM>;
@@ -483,12 +487,16 @@ template hipError_t launch_pair_counts_p<CMIF_ROWS_T, CMIF_ROWS_P>(
 CMIF_ROWS_EXTERN(float, 128)
 CMIF_ROWS_EXTERN(float, 256)
 CMIF_ROWS_EXTERN(float, 512)
+CMIF_ROWS_EXTERN(float, 768)
 CMIF_ROWS_EXTERN(float, 1024)
+CMIF_ROWS_EXTERN(float, 1536)
 CMIF_ROWS_EXTERN(float, 2048)
 CMIF_ROWS_EXTERN(double, 128)
 CMIF_ROWS_EXTERN(double, 256)
 CMIF_ROWS_EXTERN(double, 512)
+CMIF_ROWS_EXTERN(double, 768)
 CMIF_ROWS_EXTERN(double, 1024)
+CMIF_ROWS_EXTERN(double, 1536)
 CMIF_ROWS_EXTERN(double, 2048)
 #undef CMIF_ROWS_EXTERN
 
@@ -498,7 +506,9 @@ hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st) {
     case 128: return launch_pair_rows_p<T, 128>(a, st);
     case 256: return launch_pair_rows_p<T, 256>(a, st);
     case 512: return launch_pair_rows_p<T, 512>(a, st);
+    case 768: return launch_pair_rows_p<T, 768>(a, st);
     case 1024: return launch_pair_rows_p<T, 1024>(a, st);
+    case 1536: return launch_pair_rows_p<T, 1536>(a, st);
     case 2048: return launch_pair_rows_p<T, 2048>(a, st);
   }
   return hipErrorInvalidValue;
@@ -510,7 +520,9 @@ hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st)
     case 128: return launch_pair_counts_p<T, 128>(a, st);
     case 256: return launch_pair_counts_p<T, 256>(a, st);
     case 512: return launch_pair_counts_p<T, 512>(a, st);
+    case 768: return launch_pair_counts_p<T, 768>(a, st);
     case 1024: return launch_pair_counts_p<T, 1024>(a, st);
+    case 1536: return launch_pair_counts_p<T, 1536>(a, st);
     case 2048: return launch_pair_counts_p<T, 2048>(a, st);
   }
   return hipErrorInvalidValue;

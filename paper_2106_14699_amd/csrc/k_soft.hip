@@ -252,7 +252,7 @@ k_soft_grad_rows(const C2<T>* __restrict__ Z, long long z_pair_stride, int QA,
 #pragma unroll
     for (int q = 0; q < R / 2; ++q) {
       const int k = lane + TEAM * q;
-      wm[q] = lds[lpad((P - k) & (P - 1))];
+      wm[q] = lds[lpad(k == 0 ? 0 : P - k)];
     }
     team_sync<TEAM>();
     if (has0) {
@@ -316,7 +316,7 @@ k_soft_grad_cols(const C2<T>* __restrict__ GH, const C2<T>* __restrict__ FO,
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int k = lane + TEAM * q;
-        const int km = (P - k) & (P - 1);
+        const int km = k == 0 ? 0 : P - k;
         C2<T> g0, g1, f0, f1;
         unpack0<T>(g[k], g[km], g0, g1);
         unpack0<T>(f[k], f[km], f0, f1);
@@ -506,7 +506,9 @@ static hipError_t launch_sgo_p(const SoftGradOutArgs<T>& a, hipStream_t st) {
       case 128: return IMPL<T, 128>(a, st);                         \
       case 256: return IMPL<T, 256>(a, st);                         \
       case 512: return IMPL<T, 512>(a, st);                         \
+      case 768: return IMPL<T, 768>(a, st);                         \
       case 1024: return IMPL<T, 1024>(a, st);                       \
+      case 1536: return IMPL<T, 1536>(a, st);                       \
       case 2048: return IMPL<T, 2048>(a, st);                       \
     }                                                               \
     return hipErrorInvalidValue;                                    \

@@ -319,6 +319,9 @@ struct PlainEntropyArgs {
 };
 hipError_t launch_plain_entropy(const PlainEntropyArgs& a, hipStream_t st);
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
+hipError_t launch_two_stage_combine(const cmif_best& grid, cmif_best* best,
+                                    cmif_best* grid_out, cmif_best* refine_out,
+                                    int n_grid, hipStream_t st);
 
 // Host-side hooks of the plan object for the allocation-free entry point
 // (noalloc.hip): the plan's device and workspace sizes, and one eager

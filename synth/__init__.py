@@ -139,6 +139,30 @@ def rotated_pair(rng, sigma, n, q, margin, shift_range, noise_sd):
     return a, b, inside, s, theta
 
 
+def truth_a_to_b(theta_deg: float, shift, n: int):
+    """The true correspondence of the rotated generators as an affine map
+    of A's pixel (x, y) to B's, 6 numbers (row-major 2 x 3): B's pixel p
+    shows A's point R(p - c) + c - s with R = [[cos t, sin t], [-sin t,
+    cos t]] in (x, y) and c the centre, so A's point x sits at B's pixel
+    R^-1 (x - c + s) + c."""
+    th = math.radians(theta_deg)
+    ct, st = math.cos(th), math.sin(th)
+    c = (n - 1) / 2.0
+    sy, sx = float(shift[0]), float(shift[1])
+    return (ct, -st, ct * (sx - c) - st * (sy - c) + c,
+            st, ct, st * (sx - c) + ct * (sy - c) + c)
+
+
+def rotated_case(seed: int, n: int, q: int):
+    """A small rotated pair like the sweep's (blur sigma 4, rotation in
+    [0, 360) deg, shift within n/10, noise 0.2, relabelled B, M_B the
+    rotation footprint) with its true transform."""
+    rng = np.random.default_rng(seed)
+    a, b, mb, s, theta = rotated_pair(rng, 4.0, n, q, n // 2, n // 10, 0.2)
+    return dict(A=a, MA=np.ones((n, n), np.uint8), B=b, MB=mb, qa=q, qb=q,
+                shift=s, theta_deg=theta, truth=truth_a_to_b(theta, s, n))
+
+
 def config3(n_angles: int = 180, size: int = 512, q: int = 16):
     """512x512, Q=16 (256 pairs), blur sigma 4 on a 1024^2 canvas; B is the
     field rotated by a seeded angle in [0, 360) deg and moved by a seeded
@@ -151,7 +175,8 @@ def config3(n_angles: int = 180, size: int = 512, q: int = 16):
     angles = [math.radians(2.0 * i) for i in range(n_angles)]
     return dict(name=f"sweep-{size}x{size}-q{q}-{n_angles}ang", A=a,
                 MA=np.ones((size, size), np.uint8), B=b, MB=mb, qa=q, qb=q,
-                angles=angles, gamma=0.5, shift=s, theta_deg=theta)
+                angles=angles, gamma=0.5, shift=s, theta_deg=theta,
+                truth=truth_a_to_b(theta, s, size))
 
 
 def table1_pair(n: int, q: int = 16):
@@ -174,7 +199,8 @@ def table1_intensities(n: int):
     fa, fb, mb, s, theta = rotated_intensities(rng, 4.0, n, n // 2, n // 10, 0.2)
     fb = np.where(mb == 1, fb, 0.0)
     return dict(name=f"table1-intensity-{n}x{n}", A=fa.astype(np.float32),
-                B=fb.astype(np.float32), MB=mb, shift=s, theta_deg=theta)
+                B=fb.astype(np.float32), MB=mb, shift=s, theta_deg=theta,
+                truth=truth_a_to_b(theta, s, n))
 
 
 def template_pair(ref: int, q: int = 16):

@@ -306,6 +306,20 @@ def _fft_sides(cm, d):
         cm.cmif_plan_free(h)
 
 
+@pytest.mark.parametrize("side,fft", [(64, 128), (65, 256), (129, 512),
+                                      (257, 768), (385, 1024), (513, 1536),
+                                      (769, 2048), (1024, 2048)])
+def test_fft_side_rule(cm, side, fft):
+    """FFT side per axis: the smallest of 128, 256, 512, 768, 1024, 1536,
+    2048 that reaches h_a + h_b - 1 (alias-free circular correlation)."""
+    d = make_desc(cm, sizes=((side, side, side, side),))
+    assert _fft_sides(cm, d)[0] == (fft, fft)
+    # one more row or column moves to the next length exactly at the boundary
+    s = 2 * side - 1
+    d = make_desc(cm, sizes=((side, 1, side, 1),))
+    assert _fft_sides(cm, d)[0][0] == fft and fft >= s
+
+
 def test_window_validation_and_fft_sides(cm):
     s = ((400, 400, 400, 400),)
     # full set: 799 -> 1024; +-100 needs max(100 + 400, 400 + 100) -> 512
@@ -315,8 +329,9 @@ def test_window_validation_and_fft_sides(cm):
     assert win == (512, 512) and scr_win < scr_full
     # one displacement at 0 needs only max(h_a, h_b)
     assert _fft_sides(cm, _window_desc(cm, s, [(0, 0, 0, 0)]))[0] == (512, 512)
-    # a window on one side only: max(300 + 400, 400 - 10) -> 1024 rows
-    assert _fft_sides(cm, _window_desc(cm, s, [(10, 300, -5, 5)]))[0] == (1024, 512)
+    # a window on one side only: max(300 + 400, 400 - 10) -> 768 rows
+    # (3 * 2^8, the smallest compiled length >= 700)
+    assert _fft_sides(cm, _window_desc(cm, s, [(10, 300, -5, 5)]))[0] == (768, 512)
     # the full set written out is the same plan as NULL
     assert _fft_sides(cm, _window_desc(cm, s, [(-399, 399, -399, 399)]))[0] == full
     for bad in [(5, 4, 0, 0), (0, 0, 3, 2), (-400, 0, 0, 0), (0, 400, 0, 0),

@@ -65,6 +65,14 @@ RAGGED = [
     (64, 65, 65, 64, 16, 16, 0.7, "fp32"),
     (33, 31, 40, 44, 9, 13, 0.5, "fp64"),
     (20, 300, 300, 20, 2, 3, 0.9, "fp32"),
+    # 3 * 2^k FFT sides (12-point first stages): 768 x 768, then 256 rows x
+    # 1536 columns (the two-wave split row transform at 1536), then 1536
+    # rows (column transforms at 1536) x 256 columns
+    (300, 280, 310, 290, 5, 6, 0.8, "fp32"),
+    (300, 280, 310, 290, 5, 6, 0.8, "fp64"),
+    (100, 700, 90, 650, 3, 4, 0.9, "fp32"),
+    (700, 60, 650, 80, 4, 3, 0.9, "fp64"),
+    (700, 60, 650, 80, 4, 3, None, "fp32"),
 ]
 
 

@@ -1,12 +1,13 @@
 """GPU: the soft-membership batch at its own sizes (16 pairs, sides drawn in
-128..384, Q 8), against the FP64 torch oracle.
+128..384, Q 8), against the FP64 torch oracle, and soft pairs large enough
+for the 1024-point row and adjoint kernels (two-wave teams with
+workgroup-level exchanges).
 
-These sizes reach the FFT lengths whose row and adjoint kernels run
-two-wave teams with workgroup-level exchanges (1024 points), next to
-one-wave teams (512 points), in one plan.  Bars as in test_gpu_soft.py:
-forward |MI - oracle| <= 1e-5 on eligible displacements (FP32 transforms),
-gradients relative L2 <= 1e-3 against FP64 autograd of the oracle, and the
-FP64 adjoint against central differences of the FP64 forward."""
+The batch reaches FFT sides 256, 512 and 768 (3 * 2^8: 12-point first
+stages) in one plan.  Bars as in test_gpu_soft.py: forward |MI - oracle| <=
+1e-5 on eligible displacements (FP32 transforms), gradients relative L2 <=
+1e-3 against FP64 autograd of the oracle, and the FP64 adjoint against
+central differences of the FP64 forward."""
 
 import numpy as np
 import pytest
@@ -18,10 +19,13 @@ pytestmark = pytest.mark.gpu
 
 SAVE = 1 << 2  # CMIF_FLAG_SAVE_FOR_BACKWARD
 
-# pairs of the batch whose FFT sides are (512, 512), (1024, 1024),
-# (1024, 1024) and (1024, 512)
 FWD_PAIRS = (0, 3, 9, 15)
 GRAD_PAIRS = (0, 3, 8)
+SIZES = (128, 256, 512, 768, 1024, 1536, 2048)
+
+
+def fft_side(n):
+    return min(p for p in SIZES if p >= n)
 
 
 def fdev(torch, a):
@@ -52,19 +56,13 @@ def batch(gpu):
                 plan=plan, A=A, B=B, MA=MA, MB=MB)
 
 
-def _p2(v):
-    p = 128
-    while p < v:
-        p *= 2
-    return p
-
-
-def test_soft_batch_full_size_covers_both_team_shapes(batch):
-    sides = {(_p2(s[0] + s[2] - 1), _p2(s[1] + s[3] - 1)) for s in batch["sizes"]}
-    assert (1024, 1024) in sides and (512, 512) in sides
-    for k in FWD_PAIRS + GRAD_PAIRS:
-        s = batch["sizes"][k]
-        assert max(_p2(s[0] + s[2] - 1), _p2(s[1] + s[3] - 1)) >= 512
+def test_soft_batch_full_size_covers_fft_sides(batch):
+    sides = {fft_side(s[0] + s[2] - 1) for s in batch["sizes"]} | \
+        {fft_side(s[1] + s[3] - 1) for s in batch["sizes"]}
+    assert {512, 768} <= sides
+    plan = batch["cm"].Plan([batch["sizes"][3]], 8, 8, mode="soft",
+                            precision="fp32")
+    assert (plan.info()["fft_h"], plan.info()["fft_w"]) == (768, 768)
 
 
 def test_soft_batch_full_size_forward(batch, oracle):
@@ -115,21 +113,61 @@ def test_soft_batch_full_size_gradients(batch, oracle):
         assert ea <= 1e-3 and eb <= 1e-3
 
 
-def test_soft_adjoint_central_differences_1024(gpu):
-    """FP64 adjoint of one batch pair whose FFT sides are 1024 (two-wave
-    teams in the adjoint's row and output kernels) against central
-    differences of the library's own FP64 forward: L = sum_chi w(chi)
-    MI(chi), fixed weights on eligible displacements."""
+def _pair_1024():
+    """A soft pair whose FFT sides are 1024 (420 x 400 against 410 x 430,
+    Q 4): two-wave teams in the soft row and adjoint kernels."""
+    return synth.random_soft_case(1024, 420, 400, 410, 430, 4, smooth=4.0)
+
+
+def test_soft_1024_forward_and_gradients(gpu, oracle):
     cm, torch = gpu
-    p = synth.config5()["pairs"][3]
+    c = _pair_1024()
+    size = (*c["MA"].shape, *c["MB"].shape)
+    plan = cm.Plan([size], 4, 4, mode="soft", precision="fp32", flags=SAVE)
+    assert (plan.info()["fft_h"], plan.info()["fft_w"]) == (1024, 1024)
+    say(f"[gpu] soft pair at FFT side 1024 {size}")
+    A, B = fdev(torch, c["PA"]), fdev(torch, c["PB"])
+    MA, MB = dev(torch, c["MA"]), dev(torch, c["MB"])
+    r = plan.compute(A, MA, B, MB, mi=True, n=True)
+    pa = f64(torch, c["PA"]).requires_grad_(True)
+    pb = f64(torch, c["PB"]).requires_grad_(True)
+    omi, _ = oracle.soft_mi_torch(oracle.soft_joint_torch(
+        pa, f64(torch, c["MA"]), pb, f64(torch, c["MB"])))
+    n = r["n"][0][0].cpu().numpy()
+    e = n >= 0.5 * n.max()
+    err = float(np.abs(r["mi"][0][0].cpu().numpy() - omi.detach().numpy())[e].max())
+    w = np.random.default_rng(77).standard_normal(n.shape) * e
+    (omi * torch.from_numpy(w)).sum().backward()
+    ga, gb = plan.backward(A, MA, B, MB, [torch.from_numpy(w[None]).cuda()])
+    ea = rel_l2(ga[0].cpu().numpy(), pa.grad.numpy())
+    eb = rel_l2(gb[0].cpu().numpy(), pb.grad.numpy())
+    say(f"eligible max|dMI| {err:.3e}; grad rel L2 A {ea:.3e} B {eb:.3e}")
+    assert err <= 1e-5
+    assert ea <= 1e-3 and eb <= 1e-3
+
+
+@pytest.mark.parametrize("which", ["1024", "768"])
+def test_soft_adjoint_central_differences_large(gpu, which):
+    """FP64 adjoint against central differences of the library's own FP64
+    forward, L = sum_chi w(chi) MI(chi) with fixed weights on eligible
+    displacements: a pair at FFT side 1024 (two-wave teams in the adjoint's
+    row and output kernels) and a batch pair at 768 (12-point stages)."""
+    cm, torch = gpu
+    if which == "1024":
+        p = _pair_1024()
+        pa0, pb0, q = p["PA"], p["PB"], 4
+    else:
+        p = synth.config5()["pairs"][3]
+        pa0, pb0, q = p["PA"], p["PB"], 8
     ha, wa = p["MA"].shape
     hb, wb = p["MB"].shape
-    assert _p2(ha + hb - 1) == 1024 and _p2(wa + wb - 1) == 1024
-    say(f"[gpu] soft FP64 adjoint vs central differences {(ha, wa, hb, wb)}")
-    sp = cm.Plan([(ha, wa, hb, wb)], 8, 8, precision="fp64", mode="soft",
+    sp = cm.Plan([(ha, wa, hb, wb)], q, q, precision="fp64", mode="soft",
                  flags=SAVE)
+    assert sp.info()["fft_h"] == int(which)
+    say(f"[gpu] soft FP64 adjoint vs central differences {(ha, wa, hb, wb)} "
+        f"fft {sp.info()['fft_h']}x{sp.info()['fft_w']}")
     MA, MB = dev(torch, p["MA"]), dev(torch, p["MB"])
-    n = sp.compute(fdev(torch, p["PA"]), MA, fdev(torch, p["PB"]), MB,
+    n = sp.compute(fdev(torch, pa0), MA, fdev(torch, pb0), MB,
                    mi=False, n=True)["n"][0][0].cpu().numpy()
     w = np.random.default_rng(9).standard_normal(n.shape) * (n >= 0.5 * n.max())
 
@@ -138,34 +176,33 @@ def test_soft_adjoint_central_differences_1024(gpu):
                         n=False)["mi"][0][0].cpu().numpy()
         return float((mi * w).sum())
 
-    sp.compute(fdev(torch, p["PA"]), MA, fdev(torch, p["PB"]), MB, mi=True,
-               n=False)
-    ga, gb = sp.backward(fdev(torch, p["PA"]), MA, fdev(torch, p["PB"]), MB,
+    sp.compute(fdev(torch, pa0), MA, fdev(torch, pb0), MB, mi=True, n=False)
+    ga, gb = sp.backward(fdev(torch, pa0), MA, fdev(torch, pb0), MB,
                          [torch.from_numpy(w[None]).cuda()])
     ga, gb = ga[0].cpu().numpy(), gb[0].cpu().numpy()
     rng = np.random.default_rng(21)
     worst = 0.0
     h = np.float32(2.0 ** -9)
-    for side, base, g in (("A", p["PA"], ga), ("B", p["PB"], gb)):
+    for side, base, g in (("A", pa0, ga), ("B", pb0, gb)):
         for _ in range(3):
-            q = int(rng.integers(0, base.shape[0]))
+            k = int(rng.integers(0, base.shape[0]))
             y = int(rng.integers(0, base.shape[1]))
             x = int(rng.integers(0, base.shape[2]))
             hp = base.copy()
             hm = base.copy()
-            hp[q, y, x] = np.float32(base[q, y, x] + h)
-            hm[q, y, x] = np.float32(base[q, y, x] - h)
-            step = float(hp[q, y, x]) - float(hm[q, y, x])
+            hp[k, y, x] = np.float32(base[k, y, x] + h)
+            hm[k, y, x] = np.float32(base[k, y, x] - h)
+            step = float(hp[k, y, x]) - float(hm[k, y, x])
             if side == "A":
-                fd = (loss(hp, p["PB"]) - loss(hm, p["PB"])) / step
+                fd = (loss(hp, pb0) - loss(hm, pb0)) / step
             else:
-                fd = (loss(p["PA"], hp) - loss(p["PA"], hm)) / step
-            err = abs(fd - g[q, y, x]) / max(abs(fd), 1e-6)
-            say(f"  {side}[{q},{y},{x}] fd {fd:.6e} adjoint {g[q, y, x]:.6e} "
+                fd = (loss(pa0, hp) - loss(pa0, hm)) / step
+            err = abs(fd - g[k, y, x]) / max(abs(fd), 1e-6)
+            say(f"  {side}[{k},{y},{x}] fd {fd:.6e} adjoint {g[k, y, x]:.6e} "
                 f"rel {err:.2e}")
             worst = max(worst, err)
-            assert err <= 1e-3, (side, q, y, x, fd, g[q, y, x])
-    say(f"adjoint vs central differences at 1024 points: worst {worst:.2e}")
+            assert err <= 1e-3, (side, k, y, x, fd, g[k, y, x])
+    say(f"adjoint vs central differences: worst {worst:.2e}")
 
 
 def test_soft_cmif_two_forwards_share_a_plan(gpu, oracle):

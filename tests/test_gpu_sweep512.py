@@ -82,4 +82,10 @@ def test_sweep_alignment_result(sweep):
     assert b["angle_index"] == 151 and (b["dy"], b["dx"]) == tuple(c["shift"])
     assert al["stats"]["flagged_pairs"] == al["stats"]["fallback_pairs"]
     assert al["stats"]["max_residual"] < 0.25
-    say(f"best {b}; stats {al['stats']}")
+    assert al["stats"]["unresolved_pairs"] == 0
+    # the paper's success measure (Sec. 5.2): mean corner error < 2 % of
+    # the width against the planted transform
+    import paper_2106_14699_amd as cm
+    err = cm.cmif_corner_error(b, (512, 512, 512, 512), c["truth"])
+    say(f"best {b}; stats {al['stats']}; corner error {err:.3f} px")
+    assert err < 0.02 * 512

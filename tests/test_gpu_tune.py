@@ -41,7 +41,7 @@ def _same(r, ref):
     ((100, 90, 80, 110), (4, 12), "fp32", FORCE),
     ((300, 260, 280, 310), (8, 8), "fp32", 0),
     ((160, 150, 170, 140), (6, 5), "fp64", 0),
-], ids=["fp32-q4x12", "fp32-forced-rerun", "fp32-p1024", "fp64"])
+], ids=["fp32-q4x12", "fp32-forced-rerun", "fp32-p768", "fp64"])
 def test_tuned_plan_matches_default(gpu, oracle, tmp_path, size, q, prec, flags):
     cm, torch = gpu
     ha, wa, hb, wb = size

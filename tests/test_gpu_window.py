@@ -158,3 +158,50 @@ def test_template_matching_window(gpu, oracle):
     assert np.abs(r["mi"][0][0].cpu().numpy() - o["mi"]).max() <= MI_TOL
     b = r["best"][0]
     assert (-b["dy"], -b["dx"]) == tuple(c["offset"]), (b, c["offset"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_gamma_window_at_fft_768(gpu, oracle, precision):
+    """Alg. 1's padded window for gamma = 0.5 on a 400 x 400 rotated pair:
+    |chi| <= 200 per axis needs P >= 600, so the windowed plan runs at 768
+    (3 * 2^8) where the full set needs 1024.  Counts, N and digests equal
+    the oracle's full map cut to the window, MI within 1e-12 of the oracle
+    and of the full plan's cut (the 1024-point plan may group the FP64
+    entropy sums over other team shapes, so bitwise equality is not
+    implied), argmax per angle by the oracle's rule."""
+    cm, torch = gpu
+    c = synth.config3(n_angles=1, size=400, q=8)
+    n, q = 400, 8
+    angles = [0.0, math.radians(round(c["theta_deg"] / 2.0) * 2.0),
+              math.radians(90.0)]
+    w = (-200, 200, -200, 200)
+    pw = cm.Plan([(n, n, n, n)], q, q, angles=angles, precision=precision,
+                 windows=[w])
+    pf = cm.Plan([(n, n, n, n)], q, q, angles=angles, precision=precision)
+    assert (pw.info()["fft_h"], pw.info()["fft_w"]) == (768, 768)
+    assert (pf.info()["fft_h"], pf.info()["fft_w"]) == (1024, 1024)
+    say(f"[gpu] gamma window +-200 on 400x400 q8 {precision} at FFT 768")
+    ins = [dev(torch, c[k]) for k in ("A", "MA", "B", "MB")]
+    rw = pw.compute(*ins, mi=True, n=True, counts=True, digest=True,
+                    per_angle=True)
+    rf = pf.compute(*ins, mi=True, n=True)
+    for k, th in enumerate(angles):
+        bw, mw = oracle.warp_nn(c["B"], c["MB"], th)
+        o = _cut(oracle.cmif_direct(c["A"], c["MA"], bw, mw, q, q, counts=True),
+                 n, n, w)
+        g_mi = rw["mi"][0][k].cpu().numpy()
+        assert np.array_equal(rw["n"][0][k].cpu().numpy(), o["n"]), k
+        assert np.array_equal(rw["counts"][0][k].cpu().numpy(), o["counts"]), k
+        dg = rw["digest"][0][k].cpu().numpy().view(np.uint64)
+        assert np.array_equal(dg, _digest(oracle, o["counts"])), k
+        err = float(np.abs(g_mi - o["mi"]).max())
+        assert err <= MI_TOL, (k, err)
+        full = rf["mi"][0][k].cpu().numpy()[200 + n - 1 - 400:200 + n,
+                                             200 + n - 1 - 400:200 + n]
+        assert float(np.abs(g_mi - full).max()) <= MI_TOL, k
+        b = rw["per_angle"][0][k]
+        g_idx = (b["dy"] + 200) * 401 + (b["dx"] + 200)
+        ok, _ = argmax_ok(oracle, o["mi"], o["n"], 0.5, g_idx)
+        assert ok, (k, b)
+        say(f"  angle {math.degrees(th):.1f}: max|dMI| {err:.2e} best "
+            f"({b['dy']},{b['dx']}) mi {b['mi']:.6f}")
