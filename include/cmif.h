@@ -130,10 +130,10 @@ enum {
    only. */
 typedef struct cmif_plan_desc {
   int32_t n_pairs;           /* image pairs handled by one call, >= 1 */
-  const int32_t* h_a;        /* [n_pairs] heights of A, 1..1024 */
-  const int32_t* w_a;        /* [n_pairs] widths of A, 1..1024 */
-  const int32_t* h_b;        /* [n_pairs] heights of B, 1..1024 */
-  const int32_t* w_b;        /* [n_pairs] widths of B, 1..1024 */
+  const int32_t* h_a;        /* [n_pairs] heights of A, 1..2048 */
+  const int32_t* w_a;        /* [n_pairs] widths of A, 1..2048 */
+  const int32_t* h_b;        /* [n_pairs] heights of B, 1..2048 */
+  const int32_t* w_b;        /* [n_pairs] widths of B, 1..2048 */
   int32_t q_a;               /* labels of A, 1..64 */
   int32_t q_b;               /* labels of B, 1..64 */
   int32_t n_angles;          /* rotation angles applied to B, >= 1 */
@@ -166,9 +166,10 @@ typedef struct cmif_plan_desc {
                                 and the argmax cover the window only, and
                                 the FFT side per axis is the smallest
                                 supported length (see cmif_plan) >=
-                                max(y1 + h_a, h_b - y0), the least that
-                                keeps the window free of circular
-                                aliasing.  HARD mode, fused
+                                max(y1 + h_a, h_b - y0, h_a, h_b): the
+                                least that keeps the window free of
+                                circular aliasing and holds both images.
+                                HARD mode, fused
                                 schedule only (otherwise
                                 CMIF_ERR_UNSUPPORTED) */
 } cmif_plan_desc;
@@ -238,7 +239,8 @@ typedef struct cmif_outputs {
 /* Builds a plan: validates the description, chooses FFT sizes (per axis
    the smallest of 128, 256, 512, 768, 1024, 1536, 2048 -- lengths 2^k and
    3 * 2^k -- that reaches S = h_a + h_b - 1, or with a window the
-   alias-free size of the window; above 2048 CMIF_ERR_UNSUPPORTED),
+   alias-free size of the window and both image sides; above 2048
+   CMIF_ERR_UNSUPPORTED: image sides up to 2048 need a window),
    workspace layout and angle batching, and computes
    the fixed-point rotation coefficients.  Touches no device memory.  On
    success *out owns host memory released by cmif_plan_free.  Errors:

@@ -17,6 +17,7 @@
 //     argmax         gamma-eligible argmax per angle, running best (Alg. 1)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -405,6 +406,7 @@ cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout&
   pr.logtab = reinterpret_cast<const double*>(pers + P.logtab_off);
   pr.xlogtab = reinterpret_cast<const double*>(pers + P.xlog_off);
   pr.rows_per_wg = 2; pr.mi = nullptr; pr.n = n_ptr;
+  pr.full_x = g.ewa == g.wa && g.ewb == g.wb;
   pr.n_angle_stride = (long long)g.sh * g.sw; pr.maxn = maxn; pr.flags = flags;
   STAGE(ST_PAIR_ROWS, nb * ((double)half * g.sh * sizeof(C64) + 4.0 * g.sh * g.sw),
         launch_pair_rows<double>(g.pw, pr, st));
@@ -520,6 +522,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pr.sh = g.sh; pr.sw = g.sw; pr.ph = g.ph; pr.nb = nb; pr.tw = tw_w;
     pr.logtab = logtab; pr.xlogtab = xlogtab; pr.rows_per_wg = P.rows_per_wg;
     pr.bpw = P.bpw;
+    pr.full_x = g.ewa == g.wa && g.ewb == g.wb;
     pr.mi = mi_ptr; pr.mi_angle_stride = map_stride;
     pr.n = n_ptr; pr.n_angle_stride = map_stride; pr.maxn = maxn; pr.flags = flags;
     pr.stats = stats;
@@ -1363,10 +1366,10 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   for (int p = 0; p < d->n_pairs; ++p) {
     PairPlan g{};
     g.ha = d->h_a[p]; g.wa = d->w_a[p]; g.hb = d->h_b[p]; g.wb = d->w_b[p];
-    if (g.ha < 1 || g.wa < 1 || g.hb < 1 || g.wb < 1 || g.ha > 1024 ||
-        g.wa > 1024 || g.hb > 1024 || g.wb > 1024) {
+    if (g.ha < 1 || g.wa < 1 || g.hb < 1 || g.wb < 1 || g.ha > kMaxP ||
+        g.wa > kMaxP || g.hb > kMaxP || g.wb > kMaxP) {
       delete P;
-      return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be in [1, 1024]");
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be in [1, 2048]");
     }
     // displacement window (default: the full set) and its alias-free FFT
     // sides: lag chi and chi +- P must not both lie in the full set
@@ -1385,8 +1388,10 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
     g.eha = 1 - y0; g.ehb = y1 + 1; g.ewa = 1 - x0; g.ewb = x1 + 1;
     g.sh = y1 - y0 + 1;
     g.sw = x1 - x0 + 1;
-    g.ph = fft_size_at_least(std::max(y1 + g.ha, g.hb - y0));
-    g.pw = fft_size_at_least(std::max(x1 + g.wa, g.wb - x0));
+    // the transforms hold whole images (the forward kernels zero-pad, they
+    // do not fold), so the side also covers both image sides
+    g.ph = fft_size_at_least(std::max({y1 + g.ha, g.hb - y0, g.ha, g.hb}));
+    g.pw = fft_size_at_least(std::max({x1 + g.wa, g.wb - x0, g.wa, g.wb}));
     if (g.ph == 0 || g.pw == 0) {
       delete P;
       return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 2048");

@@ -372,20 +372,28 @@ __device__ __forceinline__ void team2_fft(C2<T> (&v)[P / 128], C2<T>* lds_w,
                                           int l) {
   constexpr int R = P / 128;
   team_fft<T, P / 2, 64, DIR>(v, lds_w, f_half, l);
-  C2<T>* mine = cross + wave * (P / 2);
-  const C2<T>* other = cross + (1 - wave) * (P / 2);
+  // the wave index is uniform: one branch per wave instead of per-lane
+  // selects between the two halves' formulas
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  C2<T>* mine = cross + wv * (P / 2);
+  const C2<T>* other = cross + (1 - wv) * (P / 2);
 #pragma unroll
   for (int q = 0; q < R; ++q) mine[l + 64 * q] = v[q];
   __syncthreads();
+  if (wv == 0) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const C2<T> o = other[l + 64 * q];
-    const C2<T> e = wave == 0 ? v[q] : o;
-    const C2<T> od = wave == 0 ? o : v[q];
-    C2<T> w = wm[q];
-    if constexpr (DIR < 0) w.y = -w.y;
-    const C2<T> t = cmul<T>(w, od);
-    v[q] = wave == 0 ? cadd<T>(e, t) : csub<T>(e, t);
+    for (int q = 0; q < R; ++q) {
+      C2<T> w = wm[q];
+      if constexpr (DIR < 0) w.y = -w.y;
+      v[q] = cadd<T>(v[q], cmul<T>(w, other[l + 64 * q]));
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      C2<T> w = wm[q];
+      if constexpr (DIR < 0) w.y = -w.y;
+      v[q] = csub<T>(other[l + 64 * q], cmul<T>(w, v[q]));
+    }
   }
 }
 

@@ -25,6 +25,9 @@ constexpr int kMaxBatch = 16;  // angles per pipeline pass (kernel argument)
 constexpr int kMinP = 128;
 constexpr int kXlogN = 2048;   // c log2 c tabulated for integer c < kXlogN
 constexpr int kMaxP = 2048;
+// Row pass: labels of A whose exact marginals C_a are folded into S_A and N
+// together (one workgroup barrier per group)
+constexpr int kFoldA = 2;
 // FFT lengths with compiled kernels, ascending (the plan takes the smallest
 // one that reaches the alias-free size)
 constexpr int kFftSizes[] = {128, 256, 512, 768, 1024, 1536, 2048};

@@ -31,7 +31,13 @@ namespace cmif {
 
 // RERUN selects the FP64 re-run variant (angle gates, count overrides): a
 // kernel of its own so that the main pass carries none of that code.
-template <typename T, int P, int TEAM, int BPW, int NTMAX, bool RERUN>
+// ALLPOS (plans whose x displacements are the full set): every circular lag
+// enters the per-position sums, with no branch per position.  The lags that
+// carry no displacement are then displacements without overlap, whose exact
+// correlation is 0: their rounded counts are 0 (their residual is transform
+// noise like any other) and nothing derived from them is written.
+template <typename T, int P, int TEAM, int BPW, int NTMAX, bool RERUN,
+          bool ALLPOS = false>
 __global__ void __launch_bounds__(NTMAX)
 k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             long long z_pair_stride, int QA, int QB, int wa, int wb, int sh,
@@ -56,7 +62,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   double* xlt = ltab + 512;                               // c log2 c, c < kXlogN
   double* sa_l = xlt + kXlogN;                            // S_A per x
   uint32_t* n_l = reinterpret_cast<uint32_t*>(sa_l + P);  // N per x
-  uint32_t* slot = n_l + P;                               // [2][P] C_a
+  uint32_t* slot = n_l + P;                    // [2 kFoldA][P] C_a
 
   const int beta = blockIdx.y;  // angle within batch
   const int tid = threadIdx.x;
@@ -80,7 +86,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
   }
   C2<T>* lds_w = lds + (lane >> 6) * lds_elems(P / 2);  // SPLIT: per wave
-  C2<T>* cross = reinterpret_cast<C2<T>*>(slot + 2 * P) + team * 2 * P;
+  C2<T>* cross = reinterpret_cast<C2<T>*>(slot + 2 * kFoldA * P) + team * 2 * P;
   int nfft = 0;  // alternates the exchange buffers of consecutive transforms
   auto row_fft = [&](C2<T> (&v)[R]) {
     if constexpr (SPLIT) {
@@ -101,7 +107,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 
   const int i_end = min(sh, (int)(blockIdx.x + 1) * rpw);
   for (int i = blockIdx.x * rpw; i < i_end; ++i) {
-    for (int x = tid; x < 2 * P; x += NT) slot[x] = 0u;
+    for (int x = tid; x < 2 * kFoldA * P; x += NT) slot[x] = 0u;
     for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
     __syncthreads();
     const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T, P>(i);
@@ -126,7 +132,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
                                     tile_stride, lane, nu0, nu1);
     }
     for (int a = 0; a < QA; ++a) {
-      uint32_t* sl = slot + (a & 1) * P;
+      uint32_t* sl = slot + (a % (2 * kFoldA)) * P;
       uint32_t ca[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) ca[q] = 0u;
@@ -176,7 +182,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         uint32_t big = 0u;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          if (circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
+          if (ALLPOS || circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
             const T v0 = w[q].x * scale, v1 = w[q].y * scale;
             const T r0 = round_half_even<T>(v0), r1 = round_half_even<T>(v1);
             e0max = fmaxf(e0max, (float)fabs(v0 - r0));
@@ -197,7 +203,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
           // rare: counts beyond the table, replace the clamped entries
 #pragma unroll
           for (int q = 0; q < R; ++q) {
-            if (circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
+            if (ALLPOS || circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
               const uint32_t n0 = (uint32_t)fmax(round_half_even<T>(w[q].x * scale), (T)0);
               const uint32_t n1 =
                   has1 ? (uint32_t)fmax(round_half_even<T>(w[q].y * scale), (T)0) : 0u;
@@ -225,14 +231,23 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 #pragma unroll
       for (int q = 0; q < R; ++q)
         if (ca[q] != 0u) atomicAdd(&sl[row_out_pos<P, TEAM, SPLIT>(lane, q)], ca[q]);
-      __syncthreads();
-      // C_a of this a is complete: fold it into S_A and N
-      for (int x = tid; x < P; x += NT) {
-        const uint32_t cv = sl[x];
-        if (cv != 0u) {
-          sl[x] = 0u;
-          sa_l[x] += cv < (uint32_t)kXlogN ? xlt[cv] : xlog2x_u32(cv, ltab);
-          n_l[x] += cv;
+      // every kFoldA labels of A (and after the last): their C_a are
+      // complete, fold them into S_A and N.  The planes of consecutive
+      // groups alternate, so the next group's atomics need no second
+      // barrier.
+      if ((a + 1) % kFoldA == 0 || a + 1 == QA) {
+        __syncthreads();
+        const int a0 = a - a % kFoldA;
+        for (int x = tid; x < P; x += NT) {
+          for (int g = a0; g <= a; ++g) {
+            uint32_t* sg = slot + (g % (2 * kFoldA)) * P;
+            const uint32_t cv = sg[x];
+            if (cv != 0u) {
+              sg[x] = 0u;
+              sa_l[x] += cv < (uint32_t)kXlogN ? xlt[cv] : xlog2x_u32(cv, ltab);
+              n_l[x] += cv;
+            }
+          }
         }
       }
     }
@@ -394,11 +409,11 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
   }
 }
 
-template <typename T, int P, int BPW, int NTMAX, bool RERUN>
+template <typename T, int P, int BPW, int NTMAX, bool RERUN, bool ALLPOS = false>
 static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm,
                                 hipStream_t st) {
   constexpr int TEAM = team_for(P);
-  auto fn = k_pair_rows<T, P, TEAM, BPW, NTMAX, RERUN>;
+  auto fn = k_pair_rows<T, P, TEAM, BPW, NTMAX, RERUN, ALLPOS>;
   hipError_t e = hipFuncSetAttribute((const void*)fn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
@@ -413,12 +428,23 @@ static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm
   return hipGetLastError();
 }
 
+template <typename T, int P, int BPW, bool RERUN, bool ALLPOS>
+static hipError_t launch_pr_nt(const PairRowsArgs<T>& a, const PairRowsConfig& c,
+                               hipStream_t st) {
+  if (c.ntmax <= 256) return launch_pr_cfg<T, P, BPW, 256, RERUN, ALLPOS>(a, c.nteams, c.lds, st);
+  if (c.ntmax <= 512) return launch_pr_cfg<T, P, BPW, 512, RERUN, ALLPOS>(a, c.nteams, c.lds, st);
+  return launch_pr_cfg<T, P, BPW, 1024, RERUN, ALLPOS>(a, c.nteams, c.lds, st);
+}
+
 template <typename T, int P, int BPW, bool RERUN>
 static hipError_t launch_pr_rr(const PairRowsArgs<T>& a, const PairRowsConfig& c,
                                hipStream_t st) {
-  if (c.ntmax <= 256) return launch_pr_cfg<T, P, BPW, 256, RERUN>(a, c.nteams, c.lds, st);
-  if (c.ntmax <= 512) return launch_pr_cfg<T, P, BPW, 512, RERUN>(a, c.nteams, c.lds, st);
-  return launch_pr_cfg<T, P, BPW, 1024, RERUN>(a, c.nteams, c.lds, st);
+  // every lag outside the map is a displacement without overlap when the x
+  // displacements are the full set (window extents = image widths)
+  if constexpr (!RERUN) {
+    if (a.full_x) return launch_pr_nt<T, P, BPW, false, true>(a, c, st);
+  }
+  return launch_pr_nt<T, P, BPW, RERUN, false>(a, c, st);
 }
 
 template <typename T, int P, int BPW>

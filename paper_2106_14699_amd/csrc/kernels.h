@@ -66,6 +66,9 @@ struct PairRowsArgs {
   const double* xlogtab; // kXlogN entries: c log2 c
   int rows_per_wg;       // map rows handled by one workgroup
   int bpw;               // labels of B per team, 0 = pair_rows_config's choice
+  int full_x;            // x displacements are the full set (wa, wb are the
+                         // image widths): every lag outside the map has no
+                         // overlap
   double* mi;            // nullable, [nb][sh][sw]
   long long mi_angle_stride;
   int32_t* n;            // nullable, [nb][sh][sw]
@@ -194,7 +197,7 @@ inline size_t pair_rows_lds(size_t elem_real, int P, int nteams) {
   const bool split = elem_real == sizeof(float) && team_for(P) == 128;
   return (size_t)nteams * lds_elems(P) * 2 * elem_real +
          (512 + kXlogN) * sizeof(double) + (size_t)P * sizeof(double) +
-         3 * (size_t)P * sizeof(uint32_t) +
+         (1 + 2 * kFoldA) * (size_t)P * sizeof(uint32_t) +
          (split ? (size_t)nteams * 2 * P * 2 * elem_real : 0);
 }
 

@@ -118,7 +118,11 @@ def test_plan_rejects_bad_fields(cm, field, value, expect):
 
 def test_plan_rejects_bad_sizes_and_pointers(cm):
     assert plan_status(cm, make_desc(cm, sizes=((0, 5, 5, 5),))) == 1
-    assert plan_status(cm, make_desc(cm, sizes=((5, 5, 1025, 5),))) == 1
+    assert plan_status(cm, make_desc(cm, sizes=((5, 5, 2049, 5),))) == 1
+    # sides up to 2048 are valid, but the full set of two such images needs
+    # a transform above 2048: unsupported without a window
+    assert plan_status(cm, make_desc(cm, sizes=((5, 5, 1025, 5),))) == 0
+    assert plan_status(cm, make_desc(cm, sizes=((1500, 5, 1025, 5),))) == 2
     d = make_desc(cm)
     d.h_a = None
     assert plan_status(cm, d) == 1
@@ -332,6 +336,12 @@ def test_window_validation_and_fft_sides(cm):
     # a window on one side only: max(300 + 400, 400 - 10) -> 768 rows
     # (3 * 2^8, the smallest compiled length >= 700)
     assert _fft_sides(cm, _window_desc(cm, s, [(10, 300, -5, 5)]))[0] == (768, 512)
+    # windows on one side of 0 with unequal sides: the transform still
+    # holds both images (500 + 1 and 1000 - 500 alone would give 512)
+    assert _fft_sides(cm, _window_desc(cm, ((1, 1, 1000, 1000),),
+                                       [(500, 500, 500, 500)]))[0] == (1024, 1024)
+    assert _fft_sides(cm, _window_desc(cm, ((1000, 1000, 1, 1),),
+                                       [(-500, -500, -500, -500)]))[0] == (1024, 1024)
     # the full set written out is the same plan as NULL
     assert _fft_sides(cm, _window_desc(cm, s, [(-399, 399, -399, 399)]))[0] == full
     for bad in [(5, 4, 0, 0), (0, 0, 3, 2), (-400, 0, 0, 0), (0, 400, 0, 0),

@@ -205,3 +205,40 @@ def test_gamma_window_at_fft_768(gpu, oracle, precision):
         assert ok, (k, b)
         say(f"  angle {math.degrees(th):.1f}: max|dMI| {err:.2e} best "
             f"({b['dy']},{b['dx']}) mi {b['mi']:.6f}")
+
+
+def test_template_matching_2048_reference(gpu, oracle):
+    """The paper's run-time experiment shape at a 2048 x 2048 reference and
+    a 1024 x 1024 floating image cut from it: the map over every placement
+    (window [-1024, 0]^2, FFT 2048 per axis; the full displacement set would
+    need 4095).  N is the full overlap 1024^2 everywhere, MI equals the
+    oracle's direct evaluation at sampled placements (corners, centre, the
+    planted offset, random), and the planted offset is recovered."""
+    cm, torch = gpu
+    c = synth.template_pair(2048)
+    w = c["window"]
+    plan = cm.Plan([(2048, 2048, 1024, 1024)], 16, 16, windows=[w])
+    assert (plan.info()["fft_h"], plan.info()["fft_w"]) == (2048, 2048)
+    say(f"[gpu] template 2048/1024 offset {c['offset']}")
+    r = plan.compute(dev(torch, c["A"]), None, dev(torch, c["B"]), None,
+                     mi=True, n=True, best=True)
+    n = r["n"][0][0].cpu().numpy()
+    mi = r["mi"][0][0].cpu().numpy()
+    assert n.shape == (1025, 1025) and np.all(n == 1024 * 1024)
+    rng = np.random.default_rng(2048)
+    off = c["offset"]
+    pts = {(0, 0), (1024, 1024), (0, 1024), (1024, 0), (512, 512),
+           (off[0], off[1])}
+    while len(pts) < 12:
+        pts.add((int(rng.integers(0, 1025)), int(rng.integers(0, 1025))))
+    ones_a = np.ones_like(c["A"])
+    ones_b = np.ones_like(c["B"])
+    for oy, ox in sorted(pts):
+        mo, no, _ = oracle.cmif_at(c["A"], ones_a, c["B"], ones_b, 16, 16,
+                                   -oy, -ox)
+        i, j = -oy - w[0], -ox - w[2]
+        assert n[i, j] == no
+        assert abs(mi[i, j] - mo) <= MI_TOL, (oy, ox, mi[i, j], mo)
+    b = r["best"][0]
+    say(f"best {b}; planted {off}")
+    assert (-b["dy"], -b["dx"]) == tuple(off)
