@@ -633,7 +633,8 @@ def main():
         "paper_table1_context": table1,
         "soft": soft,
         "launch_shapes": {k: info1[k] for k in ("rows_per_wg", "labels_per_team",
-                                                "xcd_grouping", "tuned",
+                                                "xcd_grouping", "cols_half",
+                                                "cols_maxr", "cols_ba", "tuned",
                                                 "tune_runs")},
         "graph": dict(replays=replays, captures=info1["graph_captures"],
                       stage_steps=stage_steps,

@@ -115,10 +115,16 @@ enum {
   CMIF_FLAG_PLAIN_SCHEDULE = 1u << 3,
   /* HARD, fused schedule: the first cmif_compute / cmif_align call times
      the candidate launch shapes of the pair row kernel (map rows per
-     workgroup 1, 2, 4 x labels of B per team 4, 8, 16 where they fit) and
-     the pair column kernel (XCD-grouped workgroup order on / off): one
-     untimed eager pass, then one eager pass per candidate on the call's own
-     buffers; keeps the fastest per kernel, then runs the call.  With
+     workgroup 1, 2, 4 x labels of B per team 4, 8, 16 where they fit: the
+     row pass's pair blocking over B) and of the pair column kernel
+     (XCD-grouped workgroup order on / off; FP32 also x the whole or half
+     the default tile of columns per workgroup x radix cap 16 or 8 (the
+     radix split of the column transform, e.g. 16x16x4 or 8x8x8x2 at 1024
+     points) x one or two labels of A per workgroup (pair blocking over A:
+     each F_B column read serves both products)): one untimed eager pass,
+     then eager passes on the call's own buffers until every candidate of
+     both kernels ran once; keeps the fastest per kernel, then runs the
+     call.  With
      tune_cache_path the choice is read at cmif_plan when the file holds it
      (no timing) and written after timing.  Every candidate gives the same
      counts; MI may differ in the last bits (summation order).  Ignored for
@@ -152,8 +158,10 @@ typedef struct cmif_plan_desc {
                                   "cmif-tune v1 gfx950 <Ph>x<Pw>:<S_h>x<S_w>...
                                   qa=<Q_A> qb=<Q_B> prec=<precision>
                                   batch=<angle batch> rows_per_wg=<1..8>
-                                  bpw=<0|4|8|16> xcd=<0|1>" (FFT and map
-                                  sizes of each image pair);
+                                  bpw=<0|4|8|16> xcd=<0|1> half=<0|1>
+                                  maxr=<16|8> ba=<1|2>" (FFT and map
+                                  sizes of each image pair; the last three
+                                  fields may be absent: defaults 0 16 1);
                                   unreadable or malformed lines are ignored,
                                   an unwritable file only skips the write;
                                   NULL = no file */
@@ -419,6 +427,11 @@ typedef struct cmif_plan_info {
                                  or launch order (0, the default) */
   int32_t tuned;              /* 0 default shapes, 1 timed, 2 from the cache */
   int32_t tune_runs;          /* eager passes spent timing candidates */
+  int32_t cols_half;          /* pair column kernel: half the default columns
+                                 per workgroup (1) or the default (0) */
+  int32_t cols_maxr;          /* pair column kernel: radix cap, 16 or 8 */
+  int32_t cols_ba;            /* pair column kernel: labels of A per
+                                 workgroup (pair blocking), 1 or 2 */
   int32_t reserved;
 } cmif_plan_info;
 

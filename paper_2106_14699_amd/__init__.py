@@ -107,7 +107,9 @@ class cmif_plan_info(ctypes.Structure):
                 ("rows_per_wg", ctypes.c_int32),
                 ("labels_per_team", ctypes.c_int32),
                 ("xcd_grouping", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("tune_runs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tune_runs", ctypes.c_int32), ("cols_half", ctypes.c_int32),
+                ("cols_maxr", ctypes.c_int32), ("cols_ba", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class cmif_stage_time(ctypes.Structure):

@@ -152,6 +152,9 @@ struct cmif_plan_s {
   int rows_per_wg = 1;   // pair row kernel: map rows per workgroup
   int bpw = 0;           // pair row kernel: labels of B per team (0: default)
   int xcd = 0;           // pair column kernel: XCD-grouped order
+  int pc_half = 0;       // pair column kernel: half the default columns
+  int pc_maxr = 16;      // pair column kernel: radix cap 16 or 8
+  int pc_ba = 1;         // pair column kernel: labels of A per workgroup
   int def_xcd = 0;       // the default order (set by cmif_plan)
   int def_rpw = 1;       // the default rows per workgroup (set by cmif_plan)
   int tuned = 0;         // 0 default, 1 timed, 2 read from the cache
@@ -488,6 +491,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pc.tiles = tiles; pc.nb = nb; pc.Z = z;
     pc.z_angle_stride = (long long)z_pair_slots(qa * qb) * half * g.sh;
     pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h; pc.xcd = P.xcd;
+    pc.cpw_half = P.pc_half; pc.maxr = P.pc_maxr; pc.ba = P.pc_ba;
     // A's spectra once per launch, B's once per angle, every pair's columns
     STAGE(ST_PAIR_COLS,
           (double)qa * half * g.ph * sizeof(CT) +
@@ -771,7 +775,8 @@ std::string tune_key(const cmif_plan_s* P) {
   return k.str();
 }
 
-// Reads "<key> rows_per_wg=R bpw=B xcd=X" lines; true if the key is found.
+// Reads "<key> rows_per_wg=R bpw=B xcd=X half=H maxr=M ba=A" lines (the
+// last three optional, defaults 0 16 1); true if the key is found.
 bool tune_read(cmif_plan_s* P) {
   std::ifstream f(P->tune_path);
   if (!f) return false;
@@ -779,14 +784,20 @@ bool tune_read(cmif_plan_s* P) {
   while (std::getline(f, line)) {
     const size_t at = line.find(" rows_per_wg=");
     if (at == std::string::npos || line.substr(0, at) != P->tune_key) continue;
-    int r = 0, b = 0, x = 0;
-    if (std::sscanf(line.c_str() + at, " rows_per_wg=%d bpw=%d xcd=%d", &r, &b, &x) != 3)
-      continue;
-    if (r < 1 || r > 8 || (b != 0 && b != 4 && b != 8 && b != 16) || x < 0 || x > 1)
+    int r = 0, b = 0, x = 0, h = 0, m = 16, a = 1;
+    const int got = std::sscanf(line.c_str() + at,
+                                " rows_per_wg=%d bpw=%d xcd=%d half=%d maxr=%d ba=%d",
+                                &r, &b, &x, &h, &m, &a);
+    if (got != 3 && got != 6) continue;
+    if (r < 1 || r > 8 || (b != 0 && b != 4 && b != 8 && b != 16) || x < 0 || x > 1 ||
+        h < 0 || h > 1 || (m != 8 && m != 16) || a < 1 || a > 2)
       continue;
     P->rows_per_wg = r;
     P->bpw = b;
     P->xcd = x;
+    P->pc_half = h;
+    P->pc_maxr = m;
+    P->pc_ba = a;
     return true;
   }
   return false;
@@ -805,7 +816,8 @@ void tune_write(const cmif_plan_s* P) {
   }
   std::ostringstream e;
   e << P->tune_key << " rows_per_wg=" << P->rows_per_wg << " bpw=" << P->bpw
-    << " xcd=" << P->xcd;
+    << " xcd=" << P->xcd << " half=" << P->pc_half << " maxr=" << P->pc_maxr
+    << " ba=" << P->pc_ba;
   lines.push_back(e.str());
   const std::string tmp = P->tune_path + ".tmp";
   {
@@ -834,7 +846,9 @@ cmif_status stage_ms(cmif_plan_s* P, double* ms, size_t base) {
 }
 
 // Times one eager pass per candidate (the call's own inputs and outputs;
-// no stats), keeps the fastest row shape and column order.  The caller's
+// no stats), keeps the fastest row shape and column shape.  Pass k runs
+// row candidate k mod |rows| and column candidate k mod |columns|, so every
+// candidate of both kernels is timed at least once.  The caller's
 // stage-profiler records are set aside meanwhile.
 template <class F>
 cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
@@ -844,9 +858,12 @@ cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
   const bool was_on = P->prof.on;
   const size_t used0 = P->prof.used;
   P->prof.on = true;
-  struct Cand { int rpw, bpw, xcd; };
-  std::vector<Cand> cands;
-  const size_t er = P->d.precision == CMIF_PREC_FP64 ? sizeof(double) : sizeof(float);
+  struct RowCand { int rpw, bpw; };
+  struct ColCand { int xcd, half, maxr, ba; };
+  std::vector<RowCand> rows;
+  std::vector<ColCand> cols;
+  const bool fp32 = P->d.precision != CMIF_PREC_FP64;
+  const size_t er = fp32 ? sizeof(float) : sizeof(double);
   PairRowsConfig def;
   const bool have_def = pair_rows_config(er, P->pairs[0].pw, P->d.q_b, &def);
   for (int bpw : {0, 4, 8, 16}) {
@@ -858,33 +875,50 @@ cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
       }
       if (!fits || (have_def && def.bpw == bpw)) continue;
     }
-    for (int rpw : {1, 2, 4}) cands.push_back({rpw, bpw, (int)(cands.size() & 1)});
+    for (int rpw : {1, 2, 4}) rows.push_back({rpw, bpw});
   }
-  double best_rows = 1e300, best_cols[2] = {1e300, 1e300};
-  Cand pick{P->def_rpw, 0, P->def_xcd};
+  // column shapes: workgroup order, and for FP32 half the columns per
+  // workgroup, radix cap 8 and two labels of A per workgroup
+  for (int xcd : {0, 1})
+    for (int half : {0, 1})
+      for (int maxr : {16, 8})
+        for (int ba : {1, 2}) {
+          if (!fp32 && (half || maxr != 16 || ba != 1)) continue;
+          cols.push_back({xcd, half, maxr, ba});
+        }
+  double best_rows = 1e300, best_cols = 1e300;
+  RowCand rpick{P->def_rpw, 0};
+  ColCand cpick{P->def_xcd, 0, 16, 1};
   // an untimed pass first: code loading and cold caches stay out of the choice
   cmif_status s = pass(st);
   if (s == CMIF_OK) {
     double ms[ST_COUNT];
     s = stage_ms(P, ms, used0);
   }
-  for (size_t k = 0; s == CMIF_OK && k < cands.size(); ++k) {
-    const Cand& c = cands[k];
-    P->rows_per_wg = c.rpw;
-    P->bpw = c.bpw;
-    P->xcd = c.xcd;
+  const size_t npass = std::max(rows.size(), cols.size());
+  for (size_t k = 0; s == CMIF_OK && k < npass; ++k) {
+    const RowCand& rc = rows[k % rows.size()];
+    const ColCand& cc = cols[k % cols.size()];
+    P->rows_per_wg = rc.rpw;
+    P->bpw = rc.bpw;
+    P->xcd = cc.xcd;
+    P->pc_half = cc.half;
+    P->pc_maxr = cc.maxr;
+    P->pc_ba = cc.ba;
     s = pass(st);
     if (s != CMIF_OK) break;
     double ms[ST_COUNT];
     s = stage_ms(P, ms, used0);
     if (s != CMIF_OK) break;
     ++P->tune_runs;
-    if (ms[ST_PAIR_ROWS] < best_rows) {
+    if (k < rows.size() && ms[ST_PAIR_ROWS] < best_rows) {
       best_rows = ms[ST_PAIR_ROWS];
-      pick.rpw = c.rpw;
-      pick.bpw = c.bpw;
+      rpick = rc;
     }
-    best_cols[c.xcd] = std::min(best_cols[c.xcd], ms[ST_PAIR_COLS]);
+    if (k < cols.size() && ms[ST_PAIR_COLS] < best_cols) {
+      best_cols = ms[ST_PAIR_COLS];
+      cpick = cc;
+    }
   }
   P->prof.on = was_on;
   P->prof.recs.swap(saved);
@@ -893,11 +927,17 @@ cmif_status autotune(cmif_plan_s* P, hipStream_t st, F&& pass) {
     P->rows_per_wg = P->def_rpw;
     P->bpw = 0;
     P->xcd = P->def_xcd;
+    P->pc_half = 0;
+    P->pc_maxr = 16;
+    P->pc_ba = 1;
     return s;
   }
-  P->rows_per_wg = pick.rpw;
-  P->bpw = pick.bpw;
-  P->xcd = best_cols[0] < best_cols[1] ? 0 : 1;
+  P->rows_per_wg = rpick.rpw;
+  P->bpw = rpick.bpw;
+  P->xcd = cpick.xcd;
+  P->pc_half = cpick.half;
+  P->pc_maxr = cpick.maxr;
+  P->pc_ba = cpick.ba;
   P->tuned = 1;
   if (!P->tune_path.empty()) tune_write(P);
   return CMIF_OK;
@@ -1269,6 +1309,9 @@ cmif_status cmif_plan_query(cmif_plan_t plan, cmif_plan_info* info) {
   info->xcd_grouping = plan->xcd;
   info->tuned = plan->tuned;
   info->tune_runs = plan->tune_runs;
+  info->cols_half = plan->pc_half;
+  info->cols_maxr = plan->pc_maxr;
+  info->cols_ba = plan->pc_ba;
   return CMIF_OK;
 }
 
@@ -1664,6 +1707,9 @@ cmif_status cmif_align_two_stage(cmif_plan_t plan, const cmif_inputs* in,
     p2->rows_per_wg = plan->rows_per_wg;
     p2->bpw = plan->bpw;
     p2->xcd = plan->xcd;
+    p2->pc_half = plan->pc_half;
+    p2->pc_maxr = plan->pc_maxr;
+    p2->pc_ba = plan->pc_ba;
     const uint8_t* la = in->labels_a[p];
     const uint8_t* lb = in->labels_b[p];
     const uint8_t* ma = in->mask_a ? in->mask_a[p] : nullptr;

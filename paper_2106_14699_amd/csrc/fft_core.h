@@ -207,21 +207,24 @@ constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 // twiddles per stage with Ns > 1).  The twiddles of a lane are the same for
 // every transform it does, so kernels load them once (fft_load_twiddles)
 // and keep them in registers.
-constexpr int stage_radix(int n, int team, int ns) {
-  return cgcd(n / team, n / ns) % 16 == 0   ? 16
-         : cgcd(n / team, n / ns) % 12 == 0 ? 12
-         : cgcd(n / team, n / ns) % 8 == 0  ? 8
-         : cgcd(n / team, n / ns) % 4 == 0  ? 4
-         : cgcd(n / team, n / ns) % 3 == 0  ? 3
-         : cgcd(n / team, n / ns) % 2 == 0  ? 2
-                                             : 1;
+// maxr (16 or 8) caps the radix: a transform tuned for fewer, cheaper
+// stages (16) or for fewer registers per butterfly (8).
+constexpr int stage_radix(int n, int team, int ns, int maxr = 16) {
+  return maxr >= 16 && cgcd(n / team, n / ns) % 16 == 0   ? 16
+         : maxr >= 12 && cgcd(n / team, n / ns) % 12 == 0 ? 12
+         : cgcd(n / team, n / ns) % 8 == 0                 ? 8
+         : cgcd(n / team, n / ns) % 4 == 0                 ? 4
+         : cgcd(n / team, n / ns) % 3 == 0                 ? 3
+         : cgcd(n / team, n / ns) % 2 == 0                 ? 2
+                                                           : 1;
 }
 
 // true when the greedy radices split n completely over a team
-constexpr bool fft_plan_ok(int n, int team, int ns = 1) {
+constexpr bool fft_plan_ok(int n, int team, int ns = 1, int maxr = 16) {
   return ns == n ? true
-                 : (stage_radix(n, team, ns) < 2 ? false
-                                                 : fft_plan_ok(n, team, ns * stage_radix(n, team, ns)));
+                 : (stage_radix(n, team, ns, maxr) < 2
+                        ? false
+                        : fft_plan_ok(n, team, ns * stage_radix(n, team, ns, maxr), maxr));
 }
 
 // supported transform lengths: 2^k or 3 * 2^k
@@ -229,28 +232,31 @@ constexpr bool fft_len_ok(int n) {
   return n >= 2 && ((n & (n - 1)) == 0 || (n % 3 == 0 && ((n / 3) & (n / 3 - 1)) == 0));
 }
 
-constexpr int fft_tw_count_from(int n, int team, int ns) {
+constexpr int fft_tw_count_from(int n, int team, int ns, int maxr) {
   return ns >= n ? 0
-                 : (ns > 1 ? (n / team / stage_radix(n, team, ns)) *
-                                 (stage_radix(n, team, ns) - 1)
+                 : (ns > 1 ? (n / team / stage_radix(n, team, ns, maxr)) *
+                                 (stage_radix(n, team, ns, maxr) - 1)
                            : 0) +
-                       fft_tw_count_from(n, team, ns * stage_radix(n, team, ns));
+                       fft_tw_count_from(n, team, ns * stage_radix(n, team, ns, maxr),
+                                         maxr);
 }
 
-template <int N, int TEAM>
-constexpr int fft_tw_count() { return fft_tw_count_from(N, TEAM, 1); }
+template <int N, int TEAM, int MAXR = 16>
+constexpr int fft_tw_count() { return fft_tw_count_from(N, TEAM, 1, MAXR); }
 
-template <typename T, int N, int TEAM>
+// A lane's twiddles in registers; MAXR is the transform's radix cap.
+template <typename T, int N, int TEAM, int MAXR = 16>
 struct FftTw {
-  C2<T> w[fft_tw_count<N, TEAM>() > 0 ? fft_tw_count<N, TEAM>() : 1];
+  static constexpr int kMaxR = MAXR;
+  C2<T> w[fft_tw_count<N, TEAM, MAXR>() > 0 ? fft_tw_count<N, TEAM, MAXR>() : 1];
 };
 
-template <typename T, int N, int TEAM, int NS, int OFF, int MUL>
-__device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM>& f,
+template <typename T, int N, int TEAM, int NS, int OFF, int MUL, int MAXR>
+__device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM, MAXR>& f,
                                              const C2<T>* __restrict__ tw,
                                              int lane) {
   constexpr int R = N / TEAM;
-  constexpr int RAD = stage_radix(N, TEAM, NS);
+  constexpr int RAD = stage_radix(N, TEAM, NS, MAXR);
   constexpr bool LAST = (NS * RAD == N);
   constexpr int BPL = R / RAD;
   constexpr int TSTRIDE = N / (NS * RAD);
@@ -265,35 +271,36 @@ __device__ __forceinline__ void fft_tw_stage(FftTw<T, N, TEAM>& f,
   }
   if constexpr (!LAST)
     fft_tw_stage<T, N, TEAM, NS * RAD,
-                 OFF + (NS > 1 ? BPL * (RAD - 1) : 0), MUL>(f, tw, lane);
+                 OFF + (NS > 1 ? BPL * (RAD - 1) : 0), MUL, MAXR>(f, tw, lane);
 }
 
 // Fills a lane's twiddles from the table tw[t] = exp(+2 pi i t / (N MUL))
 // (MUL > 1: the table of a longer transform, every MUL-th entry used).
-template <typename T, int N, int TEAM, int MUL = 1>
-__device__ __forceinline__ void fft_load_twiddles(FftTw<T, N, TEAM>& f,
+template <typename T, int N, int TEAM, int MUL = 1, int MAXR = 16>
+__device__ __forceinline__ void fft_load_twiddles(FftTw<T, N, TEAM, MAXR>& f,
                                                   const C2<T>* __restrict__ tw,
                                                   int lane) {
-  fft_tw_stage<T, N, TEAM, 1, 0, MUL>(f, tw, lane);
+  fft_tw_stage<T, N, TEAM, 1, 0, MUL, MAXR>(f, tw, lane);
 }
 
 // Twiddle source reading the N-entry table exp(+2 pi i t/N) from LDS (or any
 // memory) at every stage, for kernels whose register budget is tight.
-template <typename T, int N, int TEAM>
+template <typename T, int N, int TEAM, int MAXR = 16>
 struct FftTwTable {
+  static constexpr int kMaxR = MAXR;
   const C2<T>* tab;
 };
 
-template <typename T, int N, int TEAM, int NS, int RAD, int OFF>
-__device__ __forceinline__ C2<T> tw_get(const FftTw<T, N, TEAM>& f, int t, int m,
-                                        int k) {
+template <typename T, int N, int TEAM, int NS, int RAD, int OFF, int MAXR>
+__device__ __forceinline__ C2<T> tw_get(const FftTw<T, N, TEAM, MAXR>& f, int t,
+                                        int m, int k) {
   (void)k;
   return f.w[OFF + t * (RAD - 1) + (m - 1)];
 }
 
-template <typename T, int N, int TEAM, int NS, int RAD, int OFF>
-__device__ __forceinline__ C2<T> tw_get(const FftTwTable<T, N, TEAM>& f, int t,
-                                        int m, int k) {
+template <typename T, int N, int TEAM, int NS, int RAD, int OFF, int MAXR>
+__device__ __forceinline__ C2<T> tw_get(const FftTwTable<T, N, TEAM, MAXR>& f,
+                                        int t, int m, int k) {
   (void)t;
   return f.tab[m * k * (N / (NS * RAD))];
 }
@@ -303,7 +310,7 @@ template <typename T, int N, int TEAM, int DIR, int NS, int OFF, class TWS>
 __device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
                                           const TWS& f, int lane) {
   constexpr int R = N / TEAM;
-  constexpr int RAD = stage_radix(N, TEAM, NS);
+  constexpr int RAD = stage_radix(N, TEAM, NS, TWS::kMaxR);
   constexpr bool LAST = (NS * RAD == N);
   constexpr int BPL = R / RAD;
 #pragma unroll
@@ -316,7 +323,7 @@ __device__ __forceinline__ void fft_stage(C2<T> (&v)[N / TEAM], C2<T>* lds,
     if constexpr (NS > 1) {
 #pragma unroll
       for (int m = 1; m < RAD; ++m) {
-        C2<T> w = tw_get<T, N, TEAM, NS, RAD, OFF>(f, t, m, k);
+        C2<T> w = tw_get<T, N, TEAM, NS, RAD, OFF, TWS::kMaxR>(f, t, m, k);
         if constexpr (DIR < 0) w.y = -w.y;
         x[m] = cmul<T>(x[m], w);
       }
@@ -350,7 +357,8 @@ __device__ __forceinline__ void team_fft(C2<T> (&v)[N / TEAM], C2<T>* lds,
                                          const TWS& f, int lane) {
   static_assert(N % TEAM == 0 && N / TEAM >= 2, "team too large for N");
   static_assert(fft_len_ok(N), "lengths 2^k or 3 * 2^k only");
-  static_assert(fft_plan_ok(N, TEAM), "no radix split of N over this team");
+  static_assert(fft_plan_ok(N, TEAM, 1, TWS::kMaxR),
+                "no radix split of N over this team");
   fft_stage<T, N, TEAM, DIR, 1, 0, TWS>(v, lds, f, lane);
 }
 

@@ -54,6 +54,10 @@ struct PairColsArgs {
   const uint32_t* n_items;  // device count of valid items
   int max_items;            // grid size in item mode
   int xcd;                  // XCD-grouped workgroup order: 0 off, 1 on
+  // launch shape (FP32 fused passes; 0 = default): half the default
+  // columns per workgroup, radix cap 8 instead of 16, two labels of A per
+  // workgroup (each F_B column read serves both products)
+  int cpw_half, maxr, ba;
 };
 
 template <typename T>

@@ -271,6 +271,7 @@ def test_autotune_plan_and_cache_file(cm, tmp_path):
     assert (info["tuned"], info["tune_runs"]) == (0, 0)
     assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
         == (1, 0, 0)
+    assert (info["cols_half"], info["cols_maxr"], info["cols_ba"]) == (0, 16, 1)
     ph, pw = info["fft_h"], info["fft_w"]
     key = (f"cmif-tune v1 gfx950 {ph}x{pw}:127x127 qa=4 qb=4 prec=0 "
            f"batch={info['angle_batch']}")
@@ -287,6 +288,14 @@ def test_autotune_plan_and_cache_file(cm, tmp_path):
     assert info["tuned"] == 2 and info["tune_runs"] == 0
     assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
         == (4, 8, 0)
+    # the column-pass fields of the current format
+    f.write_text(key + " rows_per_wg=2 bpw=0 xcd=1 half=1 maxr=8 ba=2\n")
+    info = _tune_plan(cm, str(f))
+    assert info["tuned"] == 2 and (info["rows_per_wg"], info["xcd_grouping"]) == (2, 1)
+    assert (info["cols_half"], info["cols_maxr"], info["cols_ba"]) == (1, 8, 2)
+    f.write_text(key + " rows_per_wg=2 bpw=0 xcd=1 half=1 maxr=12 ba=2\n")
+    assert _tune_plan(cm, str(f))["tuned"] == 0
+    f.write_text(f.read_text() + key + " rows_per_wg=4 bpw=8 xcd=0\n")
     # without the flag, or for SOFT, the file is not consulted
     assert _tune_plan(cm, str(f), flags=0)["tuned"] == 0
     assert _tune_plan(cm, str(f), mode=cm.CMIF_MODE_SOFT)["tuned"] == 0
