@@ -6,8 +6,9 @@ this package.  The product path (the HIP library and its binding) never does.
 Two parts:
   * cmif_oracle.c, plain C + OpenMP: the direct histogram method of Sec. 2.2
     (per displacement, count label pairs over the overlap, Eq. 12 entropies,
-    Eq. 2), the Alg. 1 argmax, the integer nearest-neighbour rotation, and the
-    soft (real-weight) direct method;
+    Eq. 2), the Alg. 1 argmax, the integer nearest-neighbour rotation, the
+    soft (real-weight) direct method, and the direct method on 3-D volumes
+    (the nD case of the paper's discussion);
   * soft_* below, plain PyTorch CPU ops in FP64: the soft CMIF written as
     Eq. 7 correlations evaluated with a library FFT (torch.fft) followed by the
     Eq. 12 entropies, differentiated by autograd.  It is pinned against the C
@@ -18,8 +19,8 @@ Two parts:
     per-sample steps.
 
 Every function states the passage it follows.  All parts are pinned by
-tests/test_oracle_pins.py and tests/test_kmeans_oracle.py; none is "parity
-unpinned".
+tests/test_oracle_pins.py, tests/test_oracle3d_pins.py and
+tests/test_kmeans_oracle.py; none is "parity unpinned".
 """
 
 from __future__ import annotations
@@ -76,6 +77,9 @@ def _load():
     lib.or_mi_of_joint.restype = ctypes.c_double
     lib.or_digest_weight.argtypes = [ctypes.c_uint64]
     lib.or_digest_weight.restype = ctypes.c_uint64
+    lib.or_cmif_direct3d.argtypes = [P, P, I, I, I, P, P, I, I, I, I, I, P, P,
+                                     P, I]
+    lib.or_cmif_direct3d.restype = I
     lib.or_max_threads.argtypes = []
     lib.or_max_threads.restype = I
     _lib = lib
@@ -119,6 +123,28 @@ def cmif_direct(A, MA, B, MB, qa, qb, counts=False, digest=False,
     if rc != 0:
         raise OracleError(f"or_cmif_direct failed with code {rc}")
     return dict(mi=mi, n=n, counts=cnt, digest=dig)
+
+
+def cmif_direct3d(A, MA, B, MB, qa, qb, digest=False, nthreads=0):
+    """3-D CMIF map by the direct method (Sec. 2.2 taken to volumes, as
+    the paper's discussion states the method works in nD): A [da, ha, wa],
+    B [db, hb, wb] uint8 labels, masks or None.  Returns dict(mi, n
+    [SD, SH, SW], digest [qa, qb] u64 or None); map index [k, i, j] <->
+    chi = (k - (da-1), i - (ha-1), j - (wa-1)), B read at x + chi."""
+    lib = _load()
+    A, B, MA, MB = _u8(A), _u8(B), _u8(MA), _u8(MB)
+    da, ha, wa = A.shape
+    db, hb, wb = B.shape
+    sd, sh, sw = da + db - 1, ha + hb - 1, wa + wb - 1
+    mi = np.empty((sd, sh, sw), np.float64)
+    n = np.empty((sd, sh, sw), np.int64)
+    dig = np.empty((qa, qb), np.uint64) if digest else None
+    rc = lib.or_cmif_direct3d(_ptr(A), _ptr(MA), da, ha, wa, _ptr(B), _ptr(MB),
+                              db, hb, wb, qa, qb, _ptr(mi), _ptr(n), _ptr(dig),
+                              int(nthreads))
+    if rc != 0:
+        raise OracleError(f"or_cmif_direct3d failed with code {rc}")
+    return dict(mi=mi, n=n, digest=dig)
 
 
 def cmif_at(A, MA, B, MB, qa, qb, dy, dx):
