@@ -467,6 +467,59 @@ cmif_status cmif_kmeans(const float* image, const uint8_t* mask,
                         int32_t iters, int32_t batch, double* centers,
                         uint8_t* labels, uint32_t* bad_indices, void* stream);
 
+/* 3-D label volumes.  The paper's discussion states that the method
+   carries over to nD: the correlations of Eq. 7 over three axes and the
+   entropies of Eq. 12 per displacement chi = (dz, dy, dx) give the CMIF of
+   two volumes A [d_a][h_a][w_a] and B [d_b][h_b][w_b] (row-major, z
+   slowest) over every displacement with a non-empty box overlap, dz in
+   [-(d_a-1), d_b-1] and likewise for y and x (translations only; the
+   rotation set of Alg. 1 is not taken to 3-D).  FFT sides: in-plane the
+   smallest of cmif_plan's lengths reaching h_a + h_b - 1 and w_a + w_b - 1,
+   along depth the smallest of 32, 64, 128, 256, 512 reaching d_a + d_b - 1
+   (otherwise CMIF_ERR_UNSUPPORTED). */
+typedef struct cmif_volume_desc {
+  int32_t d_a, h_a, w_a;  /* sides of A, 1..2048 */
+  int32_t d_b, h_b, w_b;  /* sides of B, 1..2048 */
+  int32_t q_a, q_b;       /* labels, 1..64 */
+  double gamma;           /* overlap fraction of Alg. 1, in [0, 1] */
+  int32_t precision;      /* CMIF_PREC_*: FP32_ROUNDED has no FP64 re-run
+                             for volumes; label pairs whose rounding residual
+                             reached 0.25 count in stats.unresolved_pairs */
+  int32_t device;         /* HIP device ordinal */
+} cmif_volume_desc;
+
+/* Alg. 1 over a volume map: the eligible displacement with the largest
+   MI, or the identity (0, 0, 0) with mi = 0 when none is positive. */
+typedef struct cmif_best3d {
+  int32_t dz, dy, dx, reserved;
+  double mi;
+  int64_t n;
+} cmif_best3d;
+
+/* Device workspace bytes of cmif_compute_volume for this description.
+   Errors: CMIF_ERR_INVALID_ARGUMENT, CMIF_ERR_UNSUPPORTED as above. */
+cmif_status cmif_volume_workspace_size(const cmif_volume_desc* desc,
+                                       size_t* bytes);
+
+/* The volume CMIF (one call, eager launches on `stream`): labels_a and
+   labels_b are device uint8 volumes, masks device uint8 or NULL (all ones).
+   Outputs, each device memory or NULL: mi and n [S_d][S_h][S_w] (S_d =
+   d_a + d_b - 1, ...; entry [k][i][j] holds chi = (k - (d_a-1), i - (h_a-1),
+   j - (w_a-1))), digest [q_a][q_b] (sum over the map of the joint count
+   times splitmix64 of the row-major map index, modulo 2^64), best (Alg. 1,
+   gamma * max N over the whole map), stats (accumulated).  workspace: at
+   least cmif_volume_workspace_size bytes of 256-byte aligned device memory,
+   overwritten.  Errors: those of the description, CMIF_ERR_INVALID_ARGUMENT
+   (NULL labels or workspace), CMIF_ERR_WORKSPACE_TOO_SMALL,
+   CMIF_ERR_NO_DEVICE, CMIF_ERR_DEVICE. */
+cmif_status cmif_compute_volume(const cmif_volume_desc* desc,
+                                const uint8_t* labels_a, const uint8_t* mask_a,
+                                const uint8_t* labels_b, const uint8_t* mask_b,
+                                double* mi, int32_t* n, uint64_t* digest,
+                                cmif_best3d* best, cmif_stats* stats,
+                                void* workspace, size_t workspace_bytes,
+                                void* stream);
+
 /* Static description of a status code. */
 const char* cmif_status_string(cmif_status status);
 

@@ -45,7 +45,8 @@ EXPORTED = ("cmif_plan", "cmif_plan_free", "cmif_workspace_size",
             "cmif_profile_enable", "cmif_profile_read", "cmif_plan_query",
             "cmif_status_string", "cmif_last_error", "cmif_kmeans",
             "cmif_compute_noalloc", "cmif_align_two_stage",
-            "cmif_corner_error")
+            "cmif_corner_error", "cmif_volume_workspace_size",
+            "cmif_compute_volume")
 NOALLOC_BYTES = 128 << 20  # CMIF_NOALLOC_BYTES
 
 _P = ctypes.c_void_p
@@ -86,6 +87,21 @@ class cmif_best(ctypes.Structure):
                 ("dx", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("angle_rad", ctypes.c_double), ("mi", ctypes.c_double),
                 ("n", ctypes.c_int64)]
+
+
+class cmif_volume_desc(ctypes.Structure):
+    _fields_ = [("d_a", ctypes.c_int32), ("h_a", ctypes.c_int32),
+                ("w_a", ctypes.c_int32), ("d_b", ctypes.c_int32),
+                ("h_b", ctypes.c_int32), ("w_b", ctypes.c_int32),
+                ("q_a", ctypes.c_int32), ("q_b", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class cmif_best3d(ctypes.Structure):
+    _fields_ = [("dz", ctypes.c_int32), ("dy", ctypes.c_int32),
+                ("dx", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mi", ctypes.c_double), ("n", ctypes.c_int64)]
 
 
 class cmif_inputs(ctypes.Structure):
@@ -175,6 +191,12 @@ def _load_lib():
                                       ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]
     lib.cmif_corner_error.restype = ctypes.c_int
+    lib.cmif_volume_workspace_size.argtypes = [ctypes.POINTER(cmif_volume_desc),
+                                               ctypes.POINTER(S)]
+    lib.cmif_volume_workspace_size.restype = ctypes.c_int
+    lib.cmif_compute_volume.argtypes = [ctypes.POINTER(cmif_volume_desc), _P, _P,
+                                        _P, _P, _P, _P, _P, _P, _P, _P, S, _P]
+    lib.cmif_compute_volume.restype = ctypes.c_int
     lib.cmif_backward.argtypes = [_P, ctypes.POINTER(cmif_inputs), _PP, _PP,
                                   _PP, _P, S, _P, S, _P]
     lib.cmif_backward.restype = ctypes.c_int
@@ -283,6 +305,87 @@ def cmif_corner_error(result: dict, sizes, truth) -> float:
     _check(_lib.cmif_corner_error(ctypes.byref(b), ha, wa, hb, wb, t,
                                   ctypes.byref(e)), "cmif_corner_error")
     return e.value
+
+
+def cmif_volume_workspace_size(desc: cmif_volume_desc) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.cmif_volume_workspace_size(ctypes.byref(desc), ctypes.byref(b)),
+           "cmif_volume_workspace_size")
+    return b.value
+
+
+def cmif_compute_volume(desc, labels_a, mask_a, labels_b, mask_b, mi, n,
+                        digest, best, stats, workspace, workspace_bytes,
+                        stream) -> None:
+    _check(_lib.cmif_compute_volume(ctypes.byref(desc), _P(labels_a),
+                                    _P(mask_a), _P(labels_b), _P(mask_b),
+                                    _P(mi), _P(n), _P(digest), _P(best),
+                                    _P(stats), _P(workspace), workspace_bytes,
+                                    _P(stream)), "cmif_compute_volume")
+
+
+def volume_desc(shape_a, shape_b, q_a, q_b, gamma=0.5, precision="fp32",
+                device=0) -> cmif_volume_desc:
+    d = cmif_volume_desc()
+    d.d_a, d.h_a, d.w_a = (int(v) for v in shape_a)
+    d.d_b, d.h_b, d.w_b = (int(v) for v in shape_b)
+    d.q_a, d.q_b = int(q_a), int(q_b)
+    d.gamma = float(gamma)
+    d.precision = {"fp32": CMIF_PREC_FP32_ROUNDED,
+                   "fp64": CMIF_PREC_FP64}[precision]
+    d.device = int(device)
+    return d
+
+
+def compute_volume(A, MA, B, MB, q_a, q_b, *, gamma=0.5, precision="fp32",
+                   mi=True, n=True, digest=False, best=True,
+                   allow_inexact=False):
+    """3-D CMIF of two uint8 label volumes (device tensors [D][H][W],
+    masks or None) through cmif_compute_volume.  Returns dict(mi, n [S_d,
+    S_h, S_w] tensors, digest [q_a, q_b] int64 tensor, best dict(dz, dy,
+    dx, mi, n), stats).  Raises CmifInexactError when FP32 label pairs were
+    flagged (volumes have no FP64 re-run), unless allow_inexact=True."""
+    import torch
+    dev = A.device
+    for t, name in ((A, "A"), (B, "B"), (MA, "MA"), (MB, "MB")):
+        if t is None:
+            continue
+        if t.dtype != torch.uint8 or t.dim() != 3 or not t.is_contiguous() \
+                or t.device != dev:
+            raise ValueError(f"{name} must be a contiguous uint8 [D][H][W] "
+                             f"tensor on {dev}")
+    if MA is not None and tuple(MA.shape) != tuple(A.shape):
+        raise ValueError("MA must have A's shape")
+    if MB is not None and tuple(MB.shape) != tuple(B.shape):
+        raise ValueError("MB must have B's shape")
+    d = volume_desc(A.shape, B.shape, q_a, q_b, gamma, precision,
+                    dev.index or 0)
+    nbytes = cmif_volume_workspace_size(d)
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    ws = buf.data_ptr() + (-buf.data_ptr()) % 256
+    shape = tuple(a + b - 1 for a, b in zip(A.shape, B.shape))
+    mi_t = torch.empty(shape, dtype=torch.float64, device=dev) if mi else None
+    n_t = torch.empty(shape, dtype=torch.int32, device=dev) if n else None
+    dg_t = (torch.empty((q_a, q_b), dtype=torch.int64, device=dev)
+            if digest else None)
+    b_t = (torch.empty((ctypes.sizeof(cmif_best3d),), dtype=torch.uint8,
+                       device=dev) if best else None)
+    st_t = torch.zeros((ctypes.sizeof(cmif_stats),), dtype=torch.uint8,
+                       device=dev)
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    cmif_compute_volume(d, A.data_ptr(), ptr(MA), B.data_ptr(), ptr(MB),
+                        ptr(mi_t), ptr(n_t), ptr(dg_t), ptr(b_t),
+                        st_t.data_ptr(), ws, nbytes,
+                        torch.cuda.current_stream(dev).cuda_stream)
+    torch.cuda.current_stream(dev).synchronize()
+    res = dict(mi=mi_t, n=n_t, digest=dg_t, stats=_stats_dict(st_t))
+    if best:
+        b = cmif_best3d.from_buffer_copy(bytes(b_t.cpu().numpy()))
+        res["best"] = dict(dz=b.dz, dy=b.dy, dx=b.dx, mi=b.mi, n=b.n)
+    del buf
+    if res["stats"]["unresolved_pairs"] and not allow_inexact:
+        raise CmifInexactError("cmif_compute_volume", res["stats"], res)
+    return res
 
 
 def cmif_backward(plan, inputs, grad_mi, grad_a, grad_b, persistent,

@@ -23,6 +23,7 @@ ARCH = "gfx950"
 # (source, object name, defines): the row kernels are compiled once per
 # (precision, FFT length) so that the build runs in parallel
 SOURCES = [("api.cpp", "api", []), ("noalloc.hip", "noalloc", []),
+           ("volume.cpp", "volume", []), ("k_volume.hip", "k_volume", []),
            ("k_forward.hip", "k_forward", []),
            ("k_pair.hip", "k_pair", []), ("k_misc.hip", "k_misc", []),
            ("k_soft.hip", "k_soft_f32", ["-DCMIF_SOFT_T=float"]),

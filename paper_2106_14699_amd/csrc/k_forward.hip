@@ -38,7 +38,7 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
            RotArgs rot,
            C2<T>* __restrict__ xrow, long long angle_stride,
            const C2<T>* __restrict__ tw, const uint32_t* __restrict__ gate,
-           cmif_stats* __restrict__ stats) {
+           cmif_stats* __restrict__ stats, long long src_stride) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int R = P / TEAM;
@@ -46,6 +46,12 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
   const int y = blockIdx.x;
   const int beta = blockIdx.y;
   if (gate != nullptr && gate[beta] == 0u) return;  // nothing to redo here
+  // batch entry beta reads its own image (the slices of a volume) when
+  // src_stride is set, else the one image under rotation beta
+  if (src_stride != 0) {
+    if (lab) lab += beta * src_stride;
+    if (msk) msk += beta * src_stride;
+  }
   const int nteams = blockDim.x / TEAM;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
@@ -223,7 +229,7 @@ static hipError_t launch_rows_p(const FwdRowsArgs<T>& a, hipStream_t st) {
   dim3 grid(a.H, a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.lab, a.msk,
                      a.memb, a.H, a.W, a.Q, a.label0, a.rot, a.xrow,
-                     a.angle_stride, a.tw, a.gate, a.stats);
+                     a.angle_stride, a.tw, a.gate, a.stats, a.src_stride);
   return hipGetLastError();
 }
 

@@ -124,9 +124,10 @@ __device__ __forceinline__ void pair_cols_run(
     return zpair0 >= 0 ? zpair0 : (a0 + ab) * QB + b;
   };
   if (fa_col == nullptr) {
-    // the B operand already holds the product spectra (plain schedule)
+    // the B operand already holds the product spectra of every pair,
+    // [pair][c][k_y] (plain schedule, volumes)
     for (int b = b_begin; b < b_end; ++b) {
-      const C2<T>* fb_col = fb_base + b * fb_label_stride;
+      const C2<T>* fb_col = fb_base + (long long)(a0 * QB + b) * fb_label_stride;
       C2<T> v[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) v[q] = fb_col[lane + TEAM * q];

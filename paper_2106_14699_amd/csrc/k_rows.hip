@@ -327,7 +327,7 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
               uint64_t* __restrict__ digest, double* __restrict__ values,
               const int4* __restrict__ items,
               const uint32_t* __restrict__ n_items,
-              int32_t* __restrict__ item_counts) {
+              int32_t* __restrict__ item_counts, long long digest_index0) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -390,7 +390,7 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
           vb[(long long)p0 * sh * sw + o] = (double)(w[q].x * scale);
           if (has1) vb[(long long)p1 * sh * sw + o] = (double)(w[q].y * scale);
         }
-        const uint64_t wgt = splitmix64((uint64_t)o);
+        const uint64_t wgt = splitmix64((uint64_t)(digest_index0 + o));
         d0 += (uint64_t)n0 * wgt;
         d1 += (uint64_t)n1 * wgt;
       }
@@ -492,7 +492,8 @@ hipError_t launch_pair_counts_p(const PairCountsArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
                      a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
                      a.sh, a.sw, a.ph, a.tw, a.counts, a.counts_angle_stride,
-                     a.digest, a.values, a.items, a.n_items, a.item_counts);
+                     a.digest, a.values, a.items, a.n_items, a.item_counts,
+                     a.digest_index0);
   return hipGetLastError();
 }
 

@@ -23,6 +23,8 @@ struct FwdRowsArgs {
   long long angle_stride;
   const C2<T>* tw;  // P_w-entry table
   const uint32_t* gate;  // nullable: angle beta runs only if gate[beta] != 0
+  long long src_stride;  // != 0: batch entry beta reads lab/msk + beta *
+                         // src_stride (hard labels; volume slices)
 };
 
 template <typename T>
@@ -97,6 +99,8 @@ struct PairCountsArgs {
   int32_t* counts;       // nullable, [nb][QA*QB][sh][sw]
   long long counts_angle_stride;
   uint64_t* digest;      // nullable, [nb][QA*QB], accumulated (zero first)
+  long long digest_index0;  // added to the map index of the digest weights
+                            // (a slice of a larger map)
   double* values;        // nullable, [nb][QA*QB][sh][sw] unrounded values
   // item mode (nullable): Z holds one pair per item slot (no angle stride);
   // item s = (angle, a, b) writes to the (angle, a*QB+b) outputs above and,
@@ -326,6 +330,34 @@ struct PlainEntropyArgs {
 };
 hipError_t launch_plain_entropy(const PlainEntropyArgs& a, hipStream_t st);
 hipError_t launch_argmax_final(const ArgmaxFinalArgs& a, hipStream_t st);
+// Volumes (k_volume.hip): depth transforms of the slice spectra, and the
+// per-pair product with the inverse depth transform.
+template <typename T>
+struct ZfftArgs {
+  const C2<T>* F2;          // [z][label][pos], z < D
+  long long z_stride;       // elements between slices
+  long long label_stride2;  // elements between labels of one slice
+  int D, Q, npos;           // slices, labels, positions (P_w/2 * P_h)
+  C2<T>* F3;                // [label][k_z][pos]
+  const C2<T>* tw;          // P_d-entry table
+};
+template <typename T>
+struct ZpairArgs {
+  const C2<T>* F3A;
+  const C2<T>* F3B;
+  int QA, QB, npos, ph, DA, DB;
+  C2<T>* G;                 // [dz][pair][pos], dz < DA + DB - 1
+  const C2<T>* tw;          // P_d-entry table
+};
+template <typename T>
+hipError_t launch_zfft(int PD, const ZfftArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_zpair(int PD, const ZpairArgs<T>& a, hipStream_t st);
+hipError_t launch_count_flags(const uint32_t* flags, int n, cmif_stats* stats,
+                              hipStream_t st);
+hipError_t launch_best3d(const cmif_best* b2, cmif_best3d* out, int sh, int da,
+                         int ha, hipStream_t st);
+
 hipError_t launch_two_stage_combine(const cmif_best& grid, cmif_best* best,
                                     cmif_best* grid_out, cmif_best* refine_out,
                                     int n_grid, hipStream_t st);

@@ -274,6 +274,36 @@ def config5(n_pairs: int = 16, q: int = 8, lo: int = 128, hi: int = 384,
                 gamma=0.5, temperature=0.01)
 
 
+def volume_pair(seed: int, shape_a, shape_b, q: int, shift, sigma: float = 2.0,
+                noise: float = 0.2, mask_density: float | None = None):
+    """Two label volumes cut from one blurred 3-D field (the 2-D recipe in
+    three axes): A = qq(F) on its box, B = perm(qq(cos(2.5 F) + noise)) on
+    the box moved by -shift, shift = (s_z, s_y, s_x).  A's voxel x then
+    shows the field point that B shows at x + shift, so the planted
+    displacement (A(x) paired with B(x + chi)) is chi = shift, returned as
+    'chi'.  Masks all ones or Bernoulli(mask_density)."""
+    rng = np.random.default_rng(seed)
+    s = tuple(int(v) for v in shift)
+    m = max(abs(v) for v in s) + 1
+    big = tuple(max(a, b) + 2 * m for a, b in zip(shape_a, shape_b))
+    f = field(rng, sigma, big)
+    za, ya, xa = (m, m, m)
+    fa = f[za:za + shape_a[0], ya:ya + shape_a[1], xa:xa + shape_a[2]]
+    zb, yb, xb = za - s[0], ya - s[1], xa - s[2]
+    fb = f[zb:zb + shape_b[0], yb:yb + shape_b[1], xb:xb + shape_b[2]]
+    fb = np.cos(2.5 * fb) + noise * rng.standard_normal(fb.shape)
+    perm = rng.permutation(q)
+    a = qq(fa, q)
+    b = perm[qq(fb, q)].astype(np.uint8)
+    if mask_density is None:
+        ma = np.ones(shape_a, np.uint8)
+        mb = np.ones(shape_b, np.uint8)
+    else:
+        ma = (rng.random(shape_a) < mask_density).astype(np.uint8)
+        mb = (rng.random(shape_b) < mask_density).astype(np.uint8)
+    return dict(A=a, MA=ma, B=b, MB=mb, q=q, chi=s)
+
+
 def random_case(seed: int, ha: int, wa: int, hb: int, wb: int, qa: int,
                 qb: int, mask_density: float | None = 0.8,
                 smooth: float | None = 1.5):

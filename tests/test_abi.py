@@ -54,6 +54,11 @@ int main(void) {
   P(cmif_plan_desc, gamma); P(cmif_plan_desc, angle_batch);
   P(cmif_plan_desc, angles_rad); P(cmif_best, angle_rad); P(cmif_best, n);
   P(cmif_stats, max_residual); P(cmif_outputs, stats);
+  printf("vdesc %zu\n", sizeof(cmif_volume_desc));
+  printf("best3d %zu\n", sizeof(cmif_best3d));
+  P(cmif_volume_desc, gamma); P(cmif_volume_desc, device);
+  P(cmif_best3d, mi); P(cmif_best3d, n);
+  printf("info %zu\n", sizeof(cmif_plan_info));
   return 0;
 }
 ''')
@@ -75,6 +80,12 @@ int main(void) {
     assert int(got["cmif_best.n"]) == cm.cmif_best.n.offset
     assert int(got["cmif_stats.max_residual"]) == cm.cmif_stats.max_residual.offset
     assert int(got["cmif_outputs.stats"]) == cm.cmif_outputs.stats.offset
+    assert int(got["vdesc"]) == ctypes.sizeof(cm.cmif_volume_desc)
+    assert int(got["best3d"]) == ctypes.sizeof(cm.cmif_best3d)
+    assert int(got["info"]) == ctypes.sizeof(cm.cmif_plan_info)
+    for st, f in (("cmif_volume_desc", "gamma"), ("cmif_volume_desc", "device"),
+                  ("cmif_best3d", "mi"), ("cmif_best3d", "n")):
+        assert int(got[f"{st}.{f}"]) == getattr(getattr(cm, st), f).offset
 
 
 def make_desc(cm, sizes=((64, 64, 64, 64),), qa=4, qb=4, angles=(0.0,),
@@ -390,3 +401,22 @@ def test_status_strings(cm):
         assert t and t not in seen
         seen.add(t)
     assert cm.cmif_status_string(99) == "unknown status"
+
+
+def test_volume_workspace_size_validation(cm):
+    d = cm.volume_desc((12, 14, 10), (9, 11, 13), 3, 4)
+    assert cm.cmif_volume_workspace_size(d) > 0
+    # depth transform above 512 points, in-plane above 2048
+    for shape_b, status in (((600, 11, 13), cm.CMIF_ERR_UNSUPPORTED),
+                            ((9, 2040, 13), cm.CMIF_ERR_UNSUPPORTED),
+                            ((0, 11, 13), cm.CMIF_ERR_INVALID_ARGUMENT)):
+        with pytest.raises(cm.CmifError) as ei:
+            cm.cmif_volume_workspace_size(cm.volume_desc((12, 14, 10), shape_b, 3, 4))
+        assert ei.value.status == status
+    for q in (0, 65):
+        with pytest.raises(cm.CmifError):
+            cm.cmif_volume_workspace_size(cm.volume_desc((4, 4, 4), (4, 4, 4), q, 2))
+    d = cm.volume_desc((4, 4, 4), (4, 4, 4), 2, 2)
+    d.gamma = 1.5
+    with pytest.raises(cm.CmifError):
+        cm.cmif_volume_workspace_size(d)

@@ -99,10 +99,11 @@ def test_counts_vs_numpy_fftn_rint(oracle):
     s = r["n"].shape
     counts = np.zeros((2, 3) + s, np.int64)
     for a in range(2):
-        fa = np.fft.rfftn(((A == a) & (MA == 1)).astype(np.float64), s=s)
+        fa = np.fft.rfftn(((A == a) & (MA == 1)).astype(np.float64), s=s, axes=(0, 1, 2))
         for b in range(3):
-            fb = np.fft.rfftn(((B == b) & (MB == 1)).astype(np.float64), s=s)
-            circ = np.fft.irfftn(np.conj(fa) * fb, s=s)
+            fb = np.fft.rfftn(((B == b) & (MB == 1)).astype(np.float64), s=s,
+                              axes=(0, 1, 2))
+            circ = np.fft.irfftn(np.conj(fa) * fb, s=s, axes=(0, 1, 2))
             full = np.roll(circ, tuple(d - 1 for d in A.shape), axis=(0, 1, 2))
             counts[a, b] = np.rint(full).astype(np.int64)
     assert np.array_equal(_digest(oracle, counts), r["digest"])
