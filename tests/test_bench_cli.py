@@ -22,5 +22,6 @@ def test_help_lists_the_switches():
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--no-cpu", "--no-plain", "--no-soft",
                  "--no-window", "--no-stress", "--no-template", "--no-table1",
+                 "--no-volume",
                  "--tune-cache", "--no-autotune", "--copy-gib"):
         assert flag in r.stdout, flag
