@@ -136,10 +136,10 @@ enum {
    only. */
 typedef struct cmif_plan_desc {
   int32_t n_pairs;           /* image pairs handled by one call, >= 1 */
-  const int32_t* h_a;        /* [n_pairs] heights of A, 1..2048 */
-  const int32_t* w_a;        /* [n_pairs] widths of A, 1..2048 */
-  const int32_t* h_b;        /* [n_pairs] heights of B, 1..2048 */
-  const int32_t* w_b;        /* [n_pairs] widths of B, 1..2048 */
+  const int32_t* h_a;        /* [n_pairs] heights of A, 1..4096 */
+  const int32_t* w_a;        /* [n_pairs] widths of A, 1..4096 */
+  const int32_t* h_b;        /* [n_pairs] heights of B, 1..4096 */
+  const int32_t* w_b;        /* [n_pairs] widths of B, 1..4096 */
   int32_t q_a;               /* labels of A, 1..64 */
   int32_t q_b;               /* labels of B, 1..64 */
   int32_t n_angles;          /* rotation angles applied to B, >= 1 */
@@ -245,10 +245,14 @@ typedef struct cmif_outputs {
 } cmif_outputs;
 
 /* Builds a plan: validates the description, chooses FFT sizes (per axis
-   the smallest of 128, 256, 512, 768, 1024, 1536, 2048 -- lengths 2^k and
-   3 * 2^k -- that reaches S = h_a + h_b - 1, or with a window the
-   alias-free size of the window and both image sides; above 2048
-   CMIF_ERR_UNSUPPORTED: image sides up to 2048 need a window),
+   the smallest of 128, 256, 512, 768, 1024, 1536, 2048, 4096 -- lengths
+   2^k and 3 * 2^k -- that reaches S = h_a + h_b - 1, or with a window the
+   alias-free size of the window and both image sides; above 4096
+   CMIF_ERR_UNSUPPORTED: image sides above 2048 need a window, as in the
+   paper's template-matching runs of Sec. 5.1 with a 4096 reference and a
+   floating image of half its side; 4096-point sides are for
+   CMIF_PREC_FP32_ROUNDED HARD plans without CMIF_FLAG_PLAIN_SCHEDULE, else
+   CMIF_ERR_UNSUPPORTED),
    workspace layout and angle batching, and computes
    the fixed-point rotation coefficients.  Touches no device memory.  On
    success *out owns host memory released by cmif_plan_free.  Errors:

@@ -32,7 +32,7 @@ SOURCES = [("api.cpp", "api", []), ("noalloc.hip", "noalloc", []),
            # plain FP64 evaluation order (no fused multiply-adds)
            ("k_kmeans.hip", "k_kmeans", ["-ffp-contract=off"])]
 for _t, _tn in (("float", "f32"), ("double", "f64")):
-    for _p in (128, 256, 512, 768, 1024, 1536, 2048):
+    for _p in (128, 256, 512, 768, 1024, 1536, 2048, 4096):
         SOURCES.append(("k_rows.hip", f"k_rows_{_tn}_{_p}",
                         [f"-DCMIF_ROWS_T={_t}", f"-DCMIF_ROWS_P={_p}"]))
 

@@ -1412,7 +1412,7 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
     if (g.ha < 1 || g.wa < 1 || g.hb < 1 || g.wb < 1 || g.ha > kMaxP ||
         g.wa > kMaxP || g.hb > kMaxP || g.wb > kMaxP) {
       delete P;
-      return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be in [1, 2048]");
+      return fail(CMIF_ERR_INVALID_ARGUMENT, "image sides must be in [1, 4096]");
     }
     // displacement window (default: the full set) and its alias-free FFT
     // sides: lag chi and chi +- P must not both lie in the full set
@@ -1437,7 +1437,18 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
     g.pw = fft_size_at_least(std::max({x1 + g.wa, g.wb - x0, g.wa, g.wb}));
     if (g.ph == 0 || g.pw == 0) {
       delete P;
-      return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 2048");
+      return fail(CMIF_ERR_UNSUPPORTED, "FFT length above 4096");
+    }
+    // 4096-point transforms: the FP32-rounded HARD path of the fused
+    // schedule (with its FP64 re-run); the FP64 and soft row kernels'
+    // per-position state does not fit the LDS at that length
+    if (std::max(g.ph, g.pw) > kMaxSoftP &&
+        (d->mode != CMIF_MODE_HARD || d->precision != CMIF_PREC_FP32_ROUNDED ||
+         (d->flags & CMIF_FLAG_PLAIN_SCHEDULE))) {
+      delete P;
+      return fail(CMIF_ERR_UNSUPPORTED,
+                  "FFT lengths above 2048 are for FP32_ROUNDED HARD plans of the "
+                  "fused schedule only");
     }
     PairRowsConfig rc;
     SoftRowsConfig sc;

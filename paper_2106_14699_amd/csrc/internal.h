@@ -24,13 +24,20 @@ namespace cmif {
 constexpr int kMaxBatch = 16;  // angles per pipeline pass (kernel argument)
 constexpr int kMinP = 128;
 constexpr int kXlogN = 2048;   // c log2 c tabulated for integer c < kXlogN
-constexpr int kMaxP = 2048;
+constexpr int kMaxP = 4096;
 // Row pass: labels of A whose exact marginals C_a are folded into S_A and N
 // together (one workgroup barrier per group)
 constexpr int kFoldA = 2;
+// Row pass: workgroups per map row.  At 4096 points the per-position state
+// of one row (C_b of every label of B for 4096 lags) does not fit one
+// workgroup's registers, so two workgroups each transform the whole row and
+// keep the state of one half of the lags.
+__host__ __device__ constexpr int lag_parts(int p) { return p >= 4096 ? 2 : 1; }
 // FFT lengths with compiled kernels, ascending (the plan takes the smallest
-// one that reaches the alias-free size)
-constexpr int kFftSizes[] = {128, 256, 512, 768, 1024, 1536, 2048};
+// one that reaches the alias-free size).  4096 points: FP32-rounded HARD
+// plans of the fused schedule only (their FP64 re-run included).
+constexpr int kFftSizes[] = {128, 256, 512, 768, 1024, 1536, 2048, 4096};
+constexpr int kMaxSoftP = 2048;  // SOFT, FP64-precision and plain plans
 
 struct RotArgs {
   int32_t c[kMaxBatch];  // round(cos(theta) * 2^16)
@@ -100,13 +107,18 @@ constexpr int col_team_for(int p) {
 // Team size of the pair column kernel: one wave per column up to P = 1024
 // (16 points per lane: radix 16, 16, 4 with two LDS exchanges and wave-level
 // barriers only), P/16 lanes above, capped so that TW teams fit 1024 lanes.
+// At 4096 points the column kernels run fewer columns than a tile per
+// workgroup, and the teams keep 16 FP32 points per lane (256 lanes) or 8
+// FP64 points (512 lanes: 16 double points with the operand registers of
+// the pair kernel do not fit).
 template <typename T>
 constexpr int pair_col_team_raw(int p) {
   return is_pow2(p) ? (p <= 1024 ? 64 : p / 16) : p / 12;
 }
 template <typename T>
 constexpr int pair_col_team(int p) {
-  return pair_col_team_raw<T>(p) * tile_width<T>() <= 1024
+  return p >= 4096 ? (sizeof(T) == 4 ? p / 16 : p / 8)
+         : pair_col_team_raw<T>(p) * tile_width<T>() <= 1024
              ? pair_col_team_raw<T>(p)
              : 1024 / tile_width<T>();
 }

@@ -158,8 +158,12 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
   }
 }
 
-template <typename T, int P, int TEAM>
-__global__ void __launch_bounds__(tile_width<T>() * TEAM)
+// CPW columns of the tile per workgroup (one team each): the whole tile
+// (TW) up to 2048 points; at 4096 points a tile's columns would need 278 KB
+// of LDS, so each workgroup takes CPW of them and reads its 16-byte pieces
+// of every row segment.
+template <typename T, int P, int TEAM, int CPW>
+__global__ void __launch_bounds__(CPW * TEAM)
 k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
            long long x_label_stride, C2<T>* __restrict__ F,
            long long f_angle_stride, long long f_label_stride,
@@ -169,7 +173,11 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
-  const int t = blockIdx.x, lbl = blockIdx.y, beta = blockIdx.z;
+  constexpr int NPART = TW / CPW;
+  constexpr int EV = 16 / (int)sizeof(C2<T>);  // elements per 16-byte vector
+  static_assert(TW % CPW == 0 && CPW % EV == 0, "column split");
+  const int t = blockIdx.x / NPART, part = blockIdx.x % NPART;
+  const int lbl = blockIdx.y, beta = blockIdx.z;
   if (gate != nullptr && gate[beta] == 0u) return;
   const int team = threadIdx.x / TEAM;
   const int lane = threadIdx.x % TEAM;
@@ -177,14 +185,17 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
                      (long long)t * H * TW;
   FftTw<T, P, TEAM> ftw;
   fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
-  // coalesced tile load (H rows of one 64-byte segment each, 16-byte
-  // vectors) into a column-swizzled LDS tile for the column reads below
+  // tile load (H rows: the workgroup's CPW columns of each 64-byte segment,
+  // 16-byte vectors) into LDS, column-swizzled when the whole segment is
+  // loaded, for the column reads below
   {
-    constexpr int EV = 16 / (int)sizeof(C2<T>);  // elements per vector
     const float4* s4 = reinterpret_cast<const float4*>(src);
-    for (int e = threadIdx.x; e < H * TW / EV; e += blockDim.x) {
-      const int y = (e * EV) / TW, col = (e * EV) % TW;
-      *reinterpret_cast<float4*>(&smem[y * TW + (col ^ stage_swz<TW>(y))]) = s4[e];
+    constexpr int VR = CPW / EV;  // vectors per row
+    for (int e = threadIdx.x; e < H * VR; e += blockDim.x) {
+      const int y = e / VR, col = (e % VR) * EV;
+      const int dcol = NPART == 1 ? (col ^ stage_swz<TW>(y)) : col;
+      *reinterpret_cast<float4*>(&smem[y * CPW + dcol]) =
+          s4[(y * TW + part * CPW + col) / EV];
     }
   }
   __syncthreads();
@@ -195,12 +206,13 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
     // source row of position y: the row itself, or (circular mode) the map
     // row whose displacement is y mod P_h
     const int sr = circ_ha > 0 ? circ_to_map(y, P, circ_ha, circ_hb) : (y < H ? y : -1);
-    v[q] = sr >= 0 ? smem[sr * TW + (team ^ stage_swz<TW>(sr))] : mk<T>((T)0, (T)0);
+    const int scol = NPART == 1 ? (team ^ stage_swz<TW>(sr)) : team;
+    v[q] = sr >= 0 ? smem[sr * CPW + scol] : mk<T>((T)0, (T)0);
   }
   __syncthreads();
   team_fft<T, P, TEAM, -1>(v, smem + team * lds_elems(P), ftw, lane);
   C2<T>* dst = F + beta * f_angle_stride + lbl * f_label_stride +
-               (long long)(t * TW + team) * P;
+               (long long)(t * TW + part * CPW + team) * P;
 #pragma unroll
   for (int q = 0; q < R; ++q) dst[lane + TEAM * q] = v[q];
 }
@@ -243,6 +255,7 @@ hipError_t launch_fwd_rows(int P, const FwdRowsArgs<T>& a, hipStream_t st) {
     case 1024: return launch_rows_p<T, 1024>(a, st);
     case 1536: return launch_rows_p<T, 1536>(a, st);
     case 2048: return launch_rows_p<T, 2048>(a, st);
+    case 4096: return launch_rows_p<T, 4096>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -251,14 +264,17 @@ template <typename T, int P>
 static hipError_t launch_cols_p(const FwdColsArgs<T>& a, hipStream_t st) {
   constexpr int TEAM = pair_col_team<T>(P);
   constexpr int TW = tile_width<T>();
-  const size_t shm = (size_t)TW * lds_elems(P) * sizeof(C2<T>);
-  auto fn = k_fwd_cols<T, P, TEAM>;
+  // the whole tile per workgroup up to 2048 points, 512 lanes' worth of
+  // columns above
+  constexpr int CPW = P <= 2048 ? TW : (512 / TEAM < TW ? 512 / TEAM : TW);
+  const size_t shm = (size_t)CPW * lds_elems(P) * sizeof(C2<T>);
+  auto fn = k_fwd_cols<T, P, TEAM, CPW>;
   hipError_t e = hipFuncSetAttribute((const void*)fn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
   if (e != hipSuccess) return e;
-  dim3 grid(a.tiles, a.Q, a.nb);
-  hipLaunchKernelGGL(fn, grid, dim3(TW * TEAM), shm, st, a.xrow, a.H,
+  dim3 grid(a.tiles * (TW / CPW), a.Q, a.nb);
+  hipLaunchKernelGGL(fn, grid, dim3(CPW * TEAM), shm, st, a.xrow, a.H,
                      a.x_angle_stride, a.x_label_stride, a.F, a.f_angle_stride,
                      a.f_label_stride, a.tw, a.gate, a.circ_ha, a.circ_hb);
   return hipGetLastError();
@@ -274,6 +290,7 @@ hipError_t launch_fwd_cols(int P, const FwdColsArgs<T>& a, hipStream_t st) {
     case 1024: return launch_cols_p<T, 1024>(a, st);
     case 1536: return launch_cols_p<T, 1536>(a, st);
     case 2048: return launch_cols_p<T, 2048>(a, st);
+    case 4096: return launch_cols_p<T, 4096>(a, st);
   }
   return hipErrorInvalidValue;
 }

@@ -19,12 +19,14 @@ namespace cmif {
 // tile, or part of it where TW teams would exceed 512 lanes (FP32) or 256
 // lanes (FP64) — at 1024 lanes the launch bound leaves 128 registers per
 // lane and the 2048-point kernel spilled.  A part writes its columns of
-// every 64-byte row segment as 32-byte (or smaller) pieces.  The launch-shape
-// tuner may also take half of the default.
+// every 64-byte row segment as 32-byte (or smaller) pieces.  At 4096 points
+// 512 lanes' worth of columns (two FP32 columns, one FP64 column).  The
+// launch-shape tuner may also take half of the default.
 template <typename T, int P>
 constexpr int pair_cols_cpw() {
   constexpr int cap = sizeof(T) == 4 ? 512 : 256;
   constexpr int team = pair_col_team<T>(P);
+  if constexpr (P >= 4096) return 512 / team >= 1 ? 512 / team : 1;
   return tile_width<T>() * team <= cap ? tile_width<T>()
                                        : (cap / team >= 2 ? cap / team : 2);
 }
@@ -338,6 +340,7 @@ hipError_t launch_pair_cols(int P, const PairColsArgs<T>& a, hipStream_t st) {
     case 1024: return launch_pc_p<T, 1024>(a, st);
     case 1536: return launch_pc_p<T, 1536>(a, st);
     case 2048: return launch_pc_p<T, 2048>(a, st);
+    case 4096: return launch_pc_p<T, 4096>(a, st);
   }
   return hipErrorInvalidValue;
 }

@@ -16,7 +16,9 @@
 //     LDS C_a accumulator (integer atomics, exact and order-free);
 //   * after each a, C_a is folded into S_A and N per displacement;
 //   * at the end S_B is subtracted per team, the team partials are summed in
-//     a fixed order, and MI = log2 N + (S_AB - S_A - S_B) / N is written.
+//     a fixed order, and MI = log2 N + (S_AB - S_A - S_B) / N is written;
+//   * at 4096 points two workgroups share a row: each transforms the whole
+//     row and keeps the state of one half of the lags (lag_parts).
 // k_pair_counts: the same row transforms, writing the rounded joint counts
 // and/or their order-free digests instead of entropies.
 #include <type_traits>
@@ -51,6 +53,10 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             const int32_t* __restrict__ ovc) {
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
+  constexpr int LP = lag_parts(P);  // workgroups per row
+  constexpr int PX = P / LP;        // lags of this workgroup
+  constexpr int RP = R / LP;        // of them per lane
+  static_assert(LP == 1 || LP == 2, "one or two lag parts");
   if constexpr (RERUN) {
     if (gate[blockIdx.y] == 0u) return;
   }
@@ -60,9 +66,9 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   C2<T>* exch = reinterpret_cast<C2<T>*>(smem_raw);
   double* ltab = reinterpret_cast<double*>(exch + (size_t)nteams * lds_elems(P));
   double* xlt = ltab + 512;                               // c log2 c, c < kXlogN
-  double* sa_l = xlt + kXlogN;                            // S_A per x
-  uint32_t* n_l = reinterpret_cast<uint32_t*>(sa_l + P);  // N per x
-  uint32_t* slot = n_l + P;                    // [2 kFoldA][P] C_a
+  double* sa_l = xlt + kXlogN;                             // S_A per x
+  uint32_t* n_l = reinterpret_cast<uint32_t*>(sa_l + PX);  // N per x
+  uint32_t* slot = n_l + PX;                    // [2 kFoldA][PX] C_a
 
   const int beta = blockIdx.y;  // angle within batch
   const int tid = threadIdx.x;
@@ -86,7 +92,14 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     fft_load_twiddles<T, P, TEAM>(ftw, tw, lane);
   }
   C2<T>* lds_w = lds + (lane >> 6) * lds_elems(P / 2);  // SPLIT: per wave
-  C2<T>* cross = reinterpret_cast<C2<T>*>(slot + 2 * kFoldA * P) + team * 2 * P;
+  C2<T>* cross = reinterpret_cast<C2<T>*>(slot + 2 * kFoldA * PX) + team * 2 * P;
+  // lag half of this workgroup (LP = 2): lane positions q = lpart * RP + qq
+  const int lpart = LP > 1 ? (int)(blockIdx.x % LP) : 0;
+  const int chunk = LP > 1 ? (int)(blockIdx.x / LP) : (int)blockIdx.x;
+  const int x0 = lpart * PX;
+  auto pos_of = [&](int qq) {
+    return row_out_pos<P, TEAM, SPLIT>(lane, lpart * RP + qq);
+  };
   int nfft = 0;  // alternates the exchange buffers of consecutive transforms
   auto row_fft = [&](C2<T> (&v)[R]) {
     if constexpr (SPLIT) {
@@ -105,26 +118,28 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
   float maxres = 0.0f;
   uint32_t nmax = 0u;
 
-  const int i_end = min(sh, (int)(blockIdx.x + 1) * rpw);
-  for (int i = blockIdx.x * rpw; i < i_end; ++i) {
-    for (int x = tid; x < 2 * kFoldA * P; x += NT) slot[x] = 0u;
-    for (int x = tid; x < P; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
+  const int i_end = min(sh, (chunk + 1) * rpw);
+  for (int i = chunk * rpw; i < i_end; ++i) {
+    for (int x = tid; x < 2 * kFoldA * PX; x += NT) slot[x] = 0u;
+    for (int x = tid; x < PX; x += NT) { sa_l[x] = 0.0; n_l[x] = 0u; }
     __syncthreads();
     const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T, P>(i);
 
-    uint32_t cb[BPW][R];
-    double sab[R];
+    uint32_t cb[BPW][RP];
+    double sab[RP];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
+    for (int q = 0; q < RP; ++q) {
       sab[q] = 0.0;
 #pragma unroll
       for (int bb = 0; bb < BPW; ++bb) cb[bb][q] = 0u;
     }
 
     // software pipeline: the raw loads of the next pack are in flight while
-    // the current pack is transformed and reduced
+    // the current pack is transformed and reduced (not at 4096 points: the
+    // registers of the loads in flight would spill there)
+    constexpr bool PIPE = LP == 1;
     C2<T> nu0[R], nu1[R];
-    {
+    if constexpr (PIPE) {
       const int b0 = b_first, b1 = b0 + 1;
       if (b0 < QB)
         load_raw<T, P, TEAM, SPLIT>(zrow + z_pair_offset<T, P>(b0, z_pair_stride),
@@ -132,22 +147,29 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
                                     tile_stride, lane, nu0, nu1);
     }
     for (int a = 0; a < QA; ++a) {
-      uint32_t* sl = slot + (a % (2 * kFoldA)) * P;
-      uint32_t ca[R];
+      uint32_t* sl = slot + (a % (2 * kFoldA)) * PX;
+      uint32_t ca[RP];
 #pragma unroll
-      for (int q = 0; q < R; ++q) ca[q] = 0u;
+      for (int q = 0; q < RP; ++q) ca[q] = 0u;
 #pragma unroll
       for (int pk = 0; pk < BPW / 2; ++pk) {
         const int b0 = b_first + 2 * pk, b1 = b0 + 1;
         const bool has0 = b0 < QB, has1 = b1 < QB;
         C2<T> w[R];
+        if constexpr (!PIPE) {
+          if (has0)
+            load_raw<T, P, TEAM, SPLIT>(
+                zrow + z_pair_offset<T, P>(a * QB + b0, z_pair_stride),
+                zrow + z_pair_offset<T, P>(a * QB + b1, z_pair_stride), has1,
+                tile_stride, lane, nu0, nu1);
+        }
         if (has0) {
           build_pack<T, P, TEAM, SPLIT>(nu0, nu1, lane, w);
         } else {
 #pragma unroll
           for (int q = 0; q < R; ++q) w[q] = mk<T>((T)0, (T)0);
         }
-        {
+        if constexpr (PIPE) {
           // next pack: (a, pk + 1), or (a + 1, 0)
           const int na = pk + 1 < BPW / 2 ? a : a + 1;
           const int nb0 = pk + 1 < BPW / 2 ? b0 + 2 : b_first;
@@ -158,6 +180,16 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
                 nb0 + 1 < QB, tile_stride, lane, nu0, nu1);
         }
         row_fft(w);
+        // this workgroup's lags (one loop per half, so that every index
+        // stays a compile-time register index)
+        C2<T> wp[RP];
+        if (LP > 1 && lpart) {
+#pragma unroll
+          for (int qq = 0; qq < RP; ++qq) wp[qq] = w[(LP - 1) * RP + qq];
+        } else {
+#pragma unroll
+          for (int qq = 0; qq < RP; ++qq) wp[qq] = w[qq];
+        }
         if constexpr (RERUN) {
           // re-run: pairs recomputed in FP64 enter with their exact counts
           // (count * P_h P_w is exact, so the rounding below returns it)
@@ -168,11 +200,11 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
             const long long mrow = (long long)i * sw;
             const long long mstride = (long long)sh * sw;
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-              const int j = circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb);
+            for (int q = 0; q < RP; ++q) {
+              const int j = circ_to_map(pos_of(q), P, wa, wb);
               if (j >= 0) {
-                if (o0 >= 0) w[q].x = (T)ovc[o0 * mstride + mrow + j] * unscale;
-                if (o1 >= 0) w[q].y = (T)ovc[o1 * mstride + mrow + j] * unscale;
+                if (o0 >= 0) wp[q].x = (T)ovc[o0 * mstride + mrow + j] * unscale;
+                if (o1 >= 0) wp[q].y = (T)ovc[o1 * mstride + mrow + j] * unscale;
               }
             }
           }
@@ -181,9 +213,9 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         float e0max = 0.0f, e1max = 0.0f;
         uint32_t big = 0u;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          if (ALLPOS || circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
-            const T v0 = w[q].x * scale, v1 = w[q].y * scale;
+        for (int q = 0; q < RP; ++q) {
+          if (ALLPOS || circ_to_map(pos_of(q), P, wa, wb) >= 0) {
+            const T v0 = wp[q].x * scale, v1 = wp[q].y * scale;
             const T r0 = round_half_even<T>(v0), r1 = round_half_even<T>(v1);
             e0max = fmaxf(e0max, (float)fabs(v0 - r0));
             e1max = fmaxf(e1max, (float)fabs(v1 - r1));
@@ -202,11 +234,11 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
         if (big >= (uint32_t)kXlogN) {
           // rare: counts beyond the table, replace the clamped entries
 #pragma unroll
-          for (int q = 0; q < R; ++q) {
-            if (ALLPOS || circ_to_map(row_out_pos<P, TEAM, SPLIT>(lane, q), P, wa, wb) >= 0) {
-              const uint32_t n0 = (uint32_t)fmax(round_half_even<T>(w[q].x * scale), (T)0);
+          for (int q = 0; q < RP; ++q) {
+            if (ALLPOS || circ_to_map(pos_of(q), P, wa, wb) >= 0) {
+              const uint32_t n0 = (uint32_t)fmax(round_half_even<T>(wp[q].x * scale), (T)0);
               const uint32_t n1 =
-                  has1 ? (uint32_t)fmax(round_half_even<T>(w[q].y * scale), (T)0) : 0u;
+                  has1 ? (uint32_t)fmax(round_half_even<T>(wp[q].y * scale), (T)0) : 0u;
               if (n0 >= (uint32_t)kXlogN)
                 sab[q] += xlog2x_u32(n0, ltab) - xlt[kXlogN - 1];
               if (n1 >= (uint32_t)kXlogN)
@@ -229,8 +261,8 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
       }
       // exact C_a = sum over all teams' b of C_ab (integer atomics)
 #pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (ca[q] != 0u) atomicAdd(&sl[row_out_pos<P, TEAM, SPLIT>(lane, q)], ca[q]);
+      for (int q = 0; q < RP; ++q)
+        if (ca[q] != 0u) atomicAdd(&sl[pos_of(q) - x0], ca[q]);
       // every kFoldA labels of A (and after the last): their C_a are
       // complete, fold them into S_A and N.  The planes of consecutive
       // groups alternate, so the next group's atomics need no second
@@ -238,9 +270,9 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
       if ((a + 1) % kFoldA == 0 || a + 1 == QA) {
         __syncthreads();
         const int a0 = a - a % kFoldA;
-        for (int x = tid; x < P; x += NT) {
+        for (int x = tid; x < PX; x += NT) {
           for (int g = a0; g <= a; ++g) {
-            uint32_t* sg = slot + (g % (2 * kFoldA)) * P;
+            uint32_t* sg = slot + (g % (2 * kFoldA)) * PX;
             const uint32_t cv = sg[x];
             if (cv != 0u) {
               sg[x] = 0u;
@@ -254,7 +286,7 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 
     // S_AB - S_B per team, then a fixed-order sum over teams
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
+    for (int q = 0; q < RP; ++q) {
       double sb = 0.0;
 #pragma unroll
       for (int bb = 0; bb < BPW; ++bb) {
@@ -266,11 +298,11 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
     __syncthreads();
     double* part = reinterpret_cast<double*>(lds);
 #pragma unroll
-    for (int q = 0; q < R; ++q) part[row_out_pos<P, TEAM, SPLIT>(lane, q)] = sab[q];
+    for (int q = 0; q < RP; ++q) part[pos_of(q) - x0] = sab[q];
     __syncthreads();
 
-    for (int x = tid; x < P; x += NT) {
-      const int j = circ_to_map(x, P, wa, wb);
+    for (int x = tid; x < PX; x += NT) {
+      const int j = circ_to_map(x0 + x, P, wa, wb);
       if (j >= 0) {
         double tsum = 0.0;
         for (int g = 0; g < nteams; ++g)
@@ -419,7 +451,7 @@ static hipError_t launch_pr_cfg(const PairRowsArgs<T>& a, int nteams, size_t shm
                                      (int)shm);
   if (e != hipSuccess) return e;
   const int rpw = a.rows_per_wg > 0 ? a.rows_per_wg : 1;
-  dim3 grid((a.sh + rpw - 1) / rpw, a.nb);
+  dim3 grid((a.sh + rpw - 1) / rpw * lag_parts(P), a.nb);
   hipLaunchKernelGGL(fn, grid, dim3(nteams * TEAM), shm, st, a.Z,
                      a.z_angle_stride, a.z_pair_stride, a.QA, a.QB, a.wa, a.wb,
                      a.sh, a.sw, a.ph, rpw, a.tw, a.logtab, a.xlogtab, a.mi,
@@ -467,6 +499,13 @@ static hipError_t launch_pr_bpw(const PairRowsArgs<T>& a, const PairRowsConfig& 
 // for the dispatchers below, which only reference these.
 template <typename T, int P>
 hipError_t launch_pair_rows_p(const PairRowsArgs<T>& a, hipStream_t st) {
+  // FP64 rows at 4096 points do not fit the LDS (plans reject them); the
+  // 4096-point FP64 object holds the count kernel of the re-run only
+  if constexpr (sizeof(T) == 8 && P >= 4096) {
+    (void)a;
+    (void)st;
+    return hipErrorInvalidValue;
+  } else {
   PairRowsConfig c;
   const bool ok = a.bpw > 0 ? pair_rows_config_bpw(sizeof(T), P, a.QB, a.bpw, &c)
                             : pair_rows_config(sizeof(T), P, a.QB, &c);
@@ -474,6 +513,7 @@ hipError_t launch_pair_rows_p(const PairRowsArgs<T>& a, hipStream_t st) {
   if (c.bpw == 4) return launch_pr_bpw<T, P, 4>(a, c, st);
   if (c.bpw == 8) return launch_pr_bpw<T, P, 8>(a, c, st);
   return launch_pr_bpw<T, P, 16>(a, c, st);
+  }
 }
 
 template <typename T, int P>
@@ -518,6 +558,7 @@ CMIF_ROWS_EXTERN(float, 768)
 CMIF_ROWS_EXTERN(float, 1024)
 CMIF_ROWS_EXTERN(float, 1536)
 CMIF_ROWS_EXTERN(float, 2048)
+CMIF_ROWS_EXTERN(float, 4096)
 CMIF_ROWS_EXTERN(double, 128)
 CMIF_ROWS_EXTERN(double, 256)
 CMIF_ROWS_EXTERN(double, 512)
@@ -525,6 +566,7 @@ CMIF_ROWS_EXTERN(double, 768)
 CMIF_ROWS_EXTERN(double, 1024)
 CMIF_ROWS_EXTERN(double, 1536)
 CMIF_ROWS_EXTERN(double, 2048)
+CMIF_ROWS_EXTERN(double, 4096)
 #undef CMIF_ROWS_EXTERN
 
 template <typename T>
@@ -537,6 +579,7 @@ hipError_t launch_pair_rows(int P, const PairRowsArgs<T>& a, hipStream_t st) {
     case 1024: return launch_pair_rows_p<T, 1024>(a, st);
     case 1536: return launch_pair_rows_p<T, 1536>(a, st);
     case 2048: return launch_pair_rows_p<T, 2048>(a, st);
+    case 4096: return launch_pair_rows_p<T, 4096>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -551,6 +594,7 @@ hipError_t launch_pair_counts(int P, const PairCountsArgs<T>& a, hipStream_t st)
     case 1024: return launch_pair_counts_p<T, 1024>(a, st);
     case 1536: return launch_pair_counts_p<T, 1536>(a, st);
     case 2048: return launch_pair_counts_p<T, 2048>(a, st);
+    case 4096: return launch_pair_counts_p<T, 4096>(a, st);
   }
   return hipErrorInvalidValue;
 }

@@ -203,9 +203,10 @@ struct PairRowsConfig {
 // buffers per team.
 inline size_t pair_rows_lds(size_t elem_real, int P, int nteams) {
   const bool split = elem_real == sizeof(float) && team_for(P) == 128;
+  const size_t px = (size_t)(P / lag_parts(P));  // lags of one workgroup
   return (size_t)nteams * lds_elems(P) * 2 * elem_real +
-         (512 + kXlogN) * sizeof(double) + (size_t)P * sizeof(double) +
-         (1 + 2 * kFoldA) * (size_t)P * sizeof(uint32_t) +
+         (512 + kXlogN) * sizeof(double) + px * sizeof(double) +
+         (1 + 2 * kFoldA) * px * sizeof(uint32_t) +
          (split ? (size_t)nteams * 2 * P * 2 * elem_real : 0);
 }
 

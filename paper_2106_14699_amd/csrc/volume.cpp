@@ -31,9 +31,10 @@ int zsize_at_least(int v) {
   return 0;
 }
 
+// in-plane lengths: those of cmif_plan up to 2048 points
 int fft_size_at_least_v(int v) {
   for (int p : kFftSizes)
-    if (p >= v) return p;
+    if (p >= v && p <= kMaxSoftP) return p;
   return 0;
 }
 
@@ -59,7 +60,7 @@ cmif_status geometry(const cmif_volume_desc* d, VolGeom* g) {
   if (!d) return err(CMIF_ERR_INVALID_ARGUMENT, "desc is NULL");
   const int s[6] = {d->d_a, d->h_a, d->w_a, d->d_b, d->h_b, d->w_b};
   for (int v : s)
-    if (v < 1 || v > kMaxP)
+    if (v < 1 || v > kMaxSoftP)
       return err(CMIF_ERR_INVALID_ARGUMENT, "volume sides must be in [1, 2048]");
   if (d->q_a < 1 || d->q_a > 64 || d->q_b < 1 || d->q_b > 64)
     return err(CMIF_ERR_INVALID_ARGUMENT, "q_a and q_b must be in [1, 64]");

@@ -129,11 +129,20 @@ def test_plan_rejects_bad_fields(cm, field, value, expect):
 
 def test_plan_rejects_bad_sizes_and_pointers(cm):
     assert plan_status(cm, make_desc(cm, sizes=((0, 5, 5, 5),))) == 1
-    assert plan_status(cm, make_desc(cm, sizes=((5, 5, 2049, 5),))) == 1
-    # sides up to 2048 are valid, but the full set of two such images needs
-    # a transform above 2048: unsupported without a window
+    assert plan_status(cm, make_desc(cm, sizes=((5, 5, 4097, 5),))) == 1
+    # sides up to 4096 are valid, but the full set of two such images needs
+    # a transform above 4096: unsupported without a window
     assert plan_status(cm, make_desc(cm, sizes=((5, 5, 1025, 5),))) == 0
-    assert plan_status(cm, make_desc(cm, sizes=((1500, 5, 1025, 5),))) == 2
+    assert plan_status(cm, make_desc(cm, sizes=((1500, 5, 1025, 5),))) == 0
+    assert plan_status(cm, make_desc(cm, sizes=((2100, 5, 2100, 5),))) == 2
+    # 4096-point transforms: FP32-rounded HARD plans of the fused schedule
+    # only (FP64 precision, SOFT mode and the plain schedule: unsupported)
+    big = ((1500, 5, 1025, 5),)
+    assert plan_status(cm, make_desc(cm, sizes=big, precision=1)) == 2
+    assert plan_status(cm, make_desc(cm, sizes=big, mode=1)) == 2
+    assert plan_status(cm, make_desc(cm, sizes=big, precision=1,
+                                     flags=cm.CMIF_FLAG_PLAIN_SCHEDULE)) == 2
+    assert plan_status(cm, make_desc(cm, sizes=((1000, 5, 1025, 5),), precision=1)) == 0
     d = make_desc(cm)
     d.h_a = None
     assert plan_status(cm, d) == 1
@@ -332,10 +341,11 @@ def _fft_sides(cm, d):
 
 @pytest.mark.parametrize("side,fft", [(64, 128), (65, 256), (129, 512),
                                       (257, 768), (385, 1024), (513, 1536),
-                                      (769, 2048), (1024, 2048)])
+                                      (769, 2048), (1024, 2048), (1025, 4096),
+                                      (2048, 4096)])
 def test_fft_side_rule(cm, side, fft):
     """FFT side per axis: the smallest of 128, 256, 512, 768, 1024, 1536,
-    2048 that reaches h_a + h_b - 1 (alias-free circular correlation)."""
+    2048, 4096 that reaches h_a + h_b - 1 (alias-free circular correlation)."""
     d = make_desc(cm, sizes=((side, side, side, side),))
     assert _fft_sides(cm, d)[0] == (fft, fft)
     # one more row or column moves to the next length exactly at the boundary
