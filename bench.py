@@ -321,14 +321,14 @@ def table1_context(cm, torch, np, synth, dev):
 
 
 def template_bench(cm, torch, np, synth, dev, reps=5):
-    """The paper's run-time experiment shape: reference side 256 .. 2048
-    (the library's longest transform; 4096 would need FFT 4096), floating
-    image half of it, the CMIF map over every placement of the
-    floating image inside the reference (a displacement window), Q 16,
-    FP32-rounded, one angle.  Median time per map (cmif_compute of MI and N)
-    and the planted offset."""
+    """The paper's run-time experiment shape: reference side 256 .. 4096,
+    floating image half of it, the CMIF map over every placement of the
+    floating image inside the reference (a displacement window; FFT side =
+    the reference side), Q 16, FP32-rounded, one angle.  Median time per map
+    (cmif_compute of MI and N) and the planted offset."""
     out = []
-    for ref in (256, 512, 1024, 2048):
+    for ref in (256, 512, 1024, 2048, 4096):
+        print(f"[bench] template {ref}/{ref // 2}", file=sys.stderr, flush=True)
         c = synth.template_pair(ref)
         half = ref // 2
         w = c["window"]

@@ -397,6 +397,7 @@ cmif_status overlap_pass(cmif_plan_s& P, const PairPlan& g, const ScratchLayout&
   pc.z_angle_stride = (long long)z_pair_slots(1) * half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh;
   pc.tw = twiddles<double>(P, pers, g.ph); pc.xcd = P.xcd;
+  pc.zg = z_group_rt<double>(g.pw);
   STAGE(ST_PAIR_COLS, nb * (double)half * (g.ph + g.sh) * sizeof(C64),
         launch_pair_cols<double>(g.ph, pc, st));
   STAGE(ST_FILL, 4.0 * nb, launch_fill_u32(maxn, 0u, nb, st));
@@ -491,6 +492,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
     pc.tiles = tiles; pc.nb = nb; pc.Z = z;
     pc.z_angle_stride = (long long)z_pair_slots(qa * qb) * half * g.sh;
     pc.z_pair_stride = (long long)half * g.sh; pc.tw = tw_h; pc.xcd = P.xcd;
+    pc.zg = z_group_rt<T>(g.pw);
     pc.cpw_half = P.pc_half; pc.maxr = P.pc_maxr; pc.ba = P.pc_ba;
     // A's spectra once per launch, B's once per angle, every pair's columns
     STAGE(ST_PAIR_COLS,
@@ -585,7 +587,7 @@ cmif_status run_pair(cmif_plan_s& P, int p, const uint8_t* la,
       qc.QA = qa; qc.QB = qb; qc.ha = g.eha; qc.hb = g.ehb; qc.sh = g.sh;
       qc.tiles = tiles64; qc.nb = nb; qc.Z = z64; qc.z_angle_stride = 0;
       qc.z_pair_stride = (long long)half * g.sh;
-      qc.tw = twiddles<double>(P, pers, g.ph);
+      qc.tw = twiddles<double>(P, pers, g.ph); qc.zg = z_group_rt<double>(g.pw);
       qc.items = items; qc.n_items = n_items; qc.max_items = P.fb_cap;
       STAGE(ST_FB_PAIR, 0.0, launch_pair_cols<double>(g.ph, qc, st));
       PairCountsArgs<double> qk{};
@@ -677,7 +679,7 @@ cmif_status run_pair_plain(cmif_plan_s& P, int p, const uint8_t* la,
     pc.QA = 1; pc.QB = 1; pc.ha = g.eha; pc.hb = g.ehb; pc.sh = g.sh;
     pc.tiles = half / tile_width<double>(); pc.nb = 1; pc.Z = z;
     pc.z_angle_stride = 0; pc.z_pair_stride = (long long)half * g.sh;
-    pc.tw = twiddles<double>(P, pers, g.ph);
+    pc.tw = twiddles<double>(P, pers, g.ph); pc.zg = z_group_rt<double>(g.pw);
     STAGE(ST_PLAIN, ((double)fstride + (double)half * g.sh) * sizeof(C64),
           launch_pair_cols<double>(g.ph, pc, st));
     PairCountsArgs<double> pk{};
@@ -1094,7 +1096,7 @@ cmif_status run_backward_pair(cmif_plan_s& P, int p, const uint8_t* ma,
   pc.tiles = tiles; pc.nb = 1; pc.Z = z;
   pc.z_angle_stride = (long long)z_pair_slots(qa * qb) * half * g.sh;
   pc.z_pair_stride = (long long)half * g.sh; pc.tw = twiddles<T>(P, pers, g.ph);
-  pc.xcd = P.xcd;
+  pc.xcd = P.xcd; pc.zg = z_group_rt<T>(g.pw);
   const double zbytes = (double)qa * qb * half * g.sh * sizeof(CT);
   STAGE(ST_PAIR_COLS,
         (double)(qa + qb) * half * g.ph * sizeof(CT) + zbytes,

@@ -64,10 +64,31 @@ constexpr int tile_width() { return 64 / (2 * (int)sizeof(T)); }
 // pieces and the interleave measured slower) one pair after the other:
 //   p * pair_elems + t * S_h TW + i * TW.
 // Z buffers and per-angle strides hold an even number of pair slots
-// (z_pair_slots).
+// (z_pair_slots).  The row kernels that read Z decide the layout by their
+// length P_w (z_group, a compile-time constant there); the column kernel,
+// whose length P_h may be another, writes the layout it is given at run time
+// (the _rt forms, group z_group_rt(P_w)).
+template <typename T>
+__host__ __device__ constexpr int z_group_rt(int ph) {
+  return sizeof(T) == 4 && ph <= 1024 ? 2 : 1;
+}
+template <typename T>
+__host__ __device__ constexpr long long z_row_offset_rt(int i, int zg) {
+  return (long long)i * zg * tile_width<T>();
+}
+template <typename T>
+__host__ __device__ constexpr long long z_pair_offset_rt(int p, long long pair_elems, int zg) {
+  // zg = 2: (p / 2) * 2 * pair_elems + (p % 2) * TW; zg = 1: p * pair_elems
+  return (long long)(p >> (zg - 1)) * zg * pair_elems +
+         (long long)(p & (zg - 1)) * tile_width<T>();
+}
+template <typename T>
+__host__ __device__ constexpr int z_tile_stride_rt(int sh, int zg) {
+  return sh * zg * tile_width<T>();
+}
 template <typename T, int P>
 __host__ __device__ constexpr int z_group() {
-  return sizeof(T) == 4 && P <= 1024 ? 2 : 1;
+  return z_group_rt<T>(P);
 }
 template <typename T, int P>
 __host__ __device__ constexpr long long z_row_offset(int i) {

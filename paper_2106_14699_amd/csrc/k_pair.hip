@@ -78,12 +78,13 @@ __device__ __forceinline__ int pc_swz(int row) {
 }
 
 // Staging + store of one pair's CPW columns (columns part*CPW .. of the
-// tile): rows i leave as 16-byte vectors into Z[pair][tile][i][TW].
+// tile): rows i leave as 16-byte vectors into Z[pair][tile][i][TW] (layout
+// group zg of the row kernels that read it).
 template <typename T, int P, int TEAM, int CPW>
 __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* smem,
                                                 C2<T>* __restrict__ zp, int ha,
                                                 int hb, int sh, int team,
-                                                int part, int lane) {
+                                                int part, int lane, int zg) {
   constexpr int R = P / TEAM;
   constexpr int EV = 16 / (int)sizeof(C2<T>);
   constexpr bool SEP = pair_cols_sep_staging<T, P, CPW>();
@@ -102,7 +103,7 @@ __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* sme
   float4* z4 = reinterpret_cast<float4*>(zp);
   for (int e = threadIdx.x; e < sh * CPW / EV; e += blockDim.x) {
     const int i = (e * EV) / CPW, col = (e * EV) % CPW;
-    store_stream16(z4 + (z_row_offset<T, P>(i) + part * CPW + col) / EV,
+    store_stream16(z4 + (z_row_offset_rt<T>(i, zg) + part * CPW + col) / EV,
                    *reinterpret_cast<const float4*>(
                        &stage[i * CPW + (col ^ pc_swz<CPW, EV>(i))]));
   }
@@ -119,7 +120,7 @@ __device__ __forceinline__ void pair_cols_run(
     int QB, const C2<T>* __restrict__ fb_base, long long fb_label_stride,
     int b_begin, int b_end, int zpair0, int ha, int hb, int sh,
     C2<T>* __restrict__ z_base, long long z_pair_stride, const TWS& ftw,
-    C2<T>* smem, int c, int team, int part, int lane) {
+    C2<T>* smem, int c, int team, int part, int lane, int zg) {
   constexpr int R = P / TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
   auto slot = [&](int ab, int b) {
@@ -135,8 +136,8 @@ __device__ __forceinline__ void pair_cols_run(
       for (int q = 0; q < R; ++q) v[q] = fb_col[lane + TEAM * q];
       team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
       pair_cols_store<T, P, TEAM, CPW>(
-          v, smem, z_base + z_pair_offset<T, P>(slot(0, b), z_pair_stride), ha, hb,
-          sh, team, part, lane);
+          v, smem, z_base + z_pair_offset_rt<T>(slot(0, b), z_pair_stride, zg), ha, hb,
+          sh, team, part, lane, zg);
     }
     return;
   }
@@ -172,8 +173,8 @@ __device__ __forceinline__ void pair_cols_run(
         for (int q = 0; q < R; ++q) v[q] = cmulc<T>(fa[ab][q], fb[q]);
         team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
         pair_cols_store<T, P, TEAM, CPW>(
-            v, smem, z_base + z_pair_offset<T, P>(slot(ab, b), z_pair_stride), ha,
-            hb, sh, team, part, lane);
+            v, smem, z_base + z_pair_offset_rt<T>(slot(ab, b), z_pair_stride, zg), ha,
+            hb, sh, team, part, lane, zg);
       }
     }
   } else {
@@ -198,8 +199,8 @@ __device__ __forceinline__ void pair_cols_run(
         }
         team_fft<T, P, TEAM, +1>(v, lds, ftw, lane);
         pair_cols_store<T, P, TEAM, CPW>(
-            v, smem, z_base + z_pair_offset<T, P>(slot(ab, b), z_pair_stride), ha,
-            hb, sh, team, part, lane);
+            v, smem, z_base + z_pair_offset_rt<T>(slot(ab, b), z_pair_stride, zg), ha,
+            hb, sh, team, part, lane, zg);
       }
     }
   }
@@ -215,7 +216,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
             C2<T>* __restrict__ Z, long long z_angle_stride,
             long long z_pair_stride, const C2<T>* __restrict__ tw,
             const int4* __restrict__ items, const uint32_t* __restrict__ n_items,
-            int xcd_groups) {
+            int xcd_groups, int zg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<T>* smem = reinterpret_cast<C2<T>*>(smem_raw);
   constexpr int TW = tile_width<T>();
@@ -241,7 +242,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     b_begin = 0;
     b_end = QB;
     zpair0 = -1;
-    z_base = Z + beta * z_angle_stride + (long long)(t / NPART) * z_tile_stride<T, P>(sh);
+    z_base = Z + beta * z_angle_stride + (long long)(t / NPART) * z_tile_stride_rt<T>(sh, zg);
   } else {
     // item list: workgroup (tile, item) runs one pair (angle, a, b) of the
     // list into slot `item` of Z
@@ -253,7 +254,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     b_begin = e.z;
     b_end = e.z + 1;
     zpair0 = it;
-    z_base = Z + (long long)(t / NPART) * z_tile_stride<T, P>(sh);
+    z_base = Z + (long long)(t / NPART) * z_tile_stride_rt<T>(sh, zg);
   }
   const int a0 = ablk * BA;
   const int team = threadIdx.x / TEAM;
@@ -271,14 +272,14 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     pair_cols_run<T, P, TEAM, CPW, BA>(fa_col, fa_label_stride, a0, QA, QB, fb_base,
                                        fb_label_stride, b_begin, b_end, zpair0, ha, hb,
                                        sh, z_base, z_pair_stride, ftw, smem, c, team,
-                                       part, lane);
+                                       part, lane, zg);
   } else {
     FftTw<T, P, TEAM, MAXR> ftw;
     fft_load_twiddles<T, P, TEAM, 1, MAXR>(ftw, tw, lane);
     pair_cols_run<T, P, TEAM, CPW, BA>(fa_col, fa_label_stride, a0, QA, QB, fb_base,
                                        fb_label_stride, b_begin, b_end, zpair0, ha, hb,
                                        sh, z_base, z_pair_stride, ftw, smem, c, team,
-                                       part, lane);
+                                       part, lane, zg);
   }
 }
 
@@ -294,6 +295,9 @@ static hipError_t launch_pc_cfg(const PairColsArgs<T>& a, hipStream_t st) {
                                      (int)shm);
   if (e != hipSuccess) return e;
   const int parts = a.tiles * NPART;
+  // the layout group of the row kernels: 2 (pairs interleaved) for FP32 rows
+  // up to 1024 points, else 1
+  if (a.zg != 1 && !(a.zg == 2 && sizeof(T) == 4)) return hipErrorInvalidValue;
   const int ablocks = (a.QA + BA - 1) / BA;
   dim3 grid = a.items ? dim3(parts, a.max_items, 1) : dim3(parts, ablocks, a.nb);
   const int xcd_groups =
@@ -301,7 +305,7 @@ static hipError_t launch_pc_cfg(const PairColsArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(fn, grid, dim3(CPW * TEAM), shm, st, a.FA, a.fa_label_stride,
                      a.FB, a.fb_angle_stride, a.fb_label_stride, a.QA, a.QB, a.ha,
                      a.hb, a.sh, a.Z, a.z_angle_stride, a.z_pair_stride, a.tw,
-                     a.items, a.n_items, xcd_groups);
+                     a.items, a.n_items, xcd_groups, a.zg);
   return hipGetLastError();
 }
 

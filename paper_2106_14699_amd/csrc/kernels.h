@@ -51,6 +51,7 @@ struct PairColsArgs {
   C2<T>* Z;
   long long z_angle_stride, z_pair_stride;
   const C2<T>* tw;  // P_h-entry table
+  int zg;           // Z layout group of the row kernels: z_group_rt<T>(P_w)
   // item mode (nullable): one (angle, a, b) per item, Z slot = item index
   const int4* items;
   const uint32_t* n_items;  // device count of valid items

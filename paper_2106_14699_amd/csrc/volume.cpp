@@ -230,7 +230,7 @@ cmif_status run_volume(const VolGeom& g, const VolLayout& L, uint8_t* ws,
     pc.QA = qa; pc.QB = qb; pc.ha = g.ha; pc.hb = g.hb; pc.sh = g.sh;
     pc.tiles = g.half / tile_width<T>(); pc.nb = 1; pc.Z = Z;
     pc.z_angle_stride = 0; pc.z_pair_stride = (long long)g.half * g.sh;
-    pc.tw = twp<T>(ws, L.tw_h, g.ph);
+    pc.tw = twp<T>(ws, L.tw_h, g.ph); pc.zg = z_group_rt<T>(g.pw);
     VTRY(launch_pair_cols<T>(g.ph, pc, st));
     PairRowsArgs<T> pr{};
     pr.Z = Z; pr.z_angle_stride = 0; pr.z_pair_stride = pc.z_pair_stride;

@@ -68,8 +68,13 @@ def test_soft_one_hot_equals_hard(gpu, oracle, precision):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", [(40, 36, 33, 45, 3, 4, 0.8),
                                   (64, 64, 64, 64, 8, 8, None),
-                                  (17, 90, 70, 20, 2, 5, 0.9)],
-                         ids=["40x36-33x45-q34", "64-q8", "17x90-70x20-q25"])
+                                  (17, 90, 70, 20, 2, 5, 0.9),
+                                  # column and row lengths on either side of
+                                  # 1024 (1536 x 128 and 128 x 1536)
+                                  (600, 30, 560, 40, 3, 4, 0.9),
+                                  (30, 600, 40, 560, 3, 4, 0.9)],
+                         ids=["40x36-33x45-q34", "64-q8", "17x90-70x20-q25",
+                              "600x30-560x40-q34", "30x600-40x560-q34"])
 def test_soft_forward_vs_oracle(gpu, oracle, precision, case):
     cm, torch = gpu
     ha, wa, hb, wb, qa, qb, dens = case
