@@ -415,9 +415,16 @@ def test_soft_one_hot_equals_hard(oracle):
     assert np.allclose(soft["mi"], hard["mi"], atol=1e-13)
 
 
-def test_soft_torch_matches_c_direct(oracle):
+@pytest.mark.parametrize("case", [(4, 11, 9, 10, 13, 3), (6, 37, 41, 29, 33, 4),
+                                  (8, 64, 20, 50, 70, 5)],
+                         ids=["11x9-10x13", "37x41-29x33", "64x20-50x70"])
+def test_soft_torch_matches_c_direct(oracle, case):
+    """The soft reference's FFT formulation (Eq. 7 through the library FFT)
+    equals the C direct soft sums, joint and MI, at sizes whose transforms
+    wrap (padding, odd sides, unequal images)."""
     import torch
-    c = synth.random_soft_case(4, 11, 9, 10, 13, 3)
+    seed, ha, wa, hb, wb, q = case
+    c = synth.random_soft_case(seed, ha, wa, hb, wb, q)
     ref = oracle.soft_direct(c["PA"], c["MA"], c["PB"], c["MB"], joint=True)
     pa = torch.tensor(c["PA"], dtype=torch.float64)
     pb = torch.tensor(c["PB"], dtype=torch.float64)
@@ -429,9 +436,12 @@ def test_soft_torch_matches_c_direct(oracle):
     assert np.allclose(mi.numpy(), ref["mi"], atol=1e-10)
 
 
-def test_soft_autograd_vs_finite_differences(oracle):
+@pytest.mark.parametrize("case", [(5, 6, 5, 5, 6, 3), (7, 14, 11, 12, 15, 4)],
+                         ids=["6x5-5x6", "14x11-12x15"])
+def test_soft_autograd_vs_finite_differences(oracle, case):
     import torch
-    c = synth.random_soft_case(5, 6, 5, 5, 6, 3)
+    seed, ha, wa, hb, wb, q = case
+    c = synth.random_soft_case(seed, ha, wa, hb, wb, q)
     ma = torch.tensor(c["MA"], dtype=torch.float64)
     mb = torch.tensor(c["MB"], dtype=torch.float64)
     pa0 = torch.tensor(c["PA"], dtype=torch.float64)
