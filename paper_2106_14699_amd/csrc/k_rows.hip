@@ -72,7 +72,11 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
 
   const int beta = blockIdx.y;  // angle within batch
   const int tid = threadIdx.x;
-  const int team = tid / TEAM;
+  // a team spans whole waves: its index is wave-uniform, and saying so
+  // keeps the per-pack label tests (has0, has1) scalar branches instead of
+  // exec-masked blocks around every load
+  static_assert(TEAM % 64 == 0, "teams of whole waves");
+  const int team = __builtin_amdgcn_readfirstlane(tid / TEAM);
   const int lane = tid % TEAM;
   C2<T>* lds = exch + team * lds_elems(P);
 
@@ -259,10 +263,10 @@ k_pair_rows(const C2<T>* __restrict__ Z, long long z_angle_stride,
           }
         }
       }
-      // exact C_a = sum over all teams' b of C_ab (integer atomics)
+      // exact C_a = sum over all teams' b of C_ab (integer atomics; adding
+      // a zero costs less than the lane-divergent branch that would skip it)
 #pragma unroll
-      for (int q = 0; q < RP; ++q)
-        if (ca[q] != 0u) atomicAdd(&sl[pos_of(q) - x0], ca[q]);
+      for (int q = 0; q < RP; ++q) atomicAdd(&sl[pos_of(q) - x0], ca[q]);
       // every kFoldA labels of A (and after the last): their C_a are
       // complete, fold them into S_A and N.  The planes of consecutive
       // groups alternate, so the next group's atomics need no second
@@ -366,7 +370,9 @@ k_pair_counts(const C2<T>* __restrict__ Z, long long z_angle_stride,
   C2<T>* exch = reinterpret_cast<C2<T>*>(smem_raw);
   const int nteams = blockDim.x / TEAM;
   const int i = blockIdx.x, beta = blockIdx.y;
-  const int tid = threadIdx.x, team = tid / TEAM, lane = tid % TEAM;
+  static_assert(TEAM % 64 == 0, "teams of whole waves");
+  const int tid = threadIdx.x, lane = tid % TEAM;
+  const int team = __builtin_amdgcn_readfirstlane(tid / TEAM);  // wave-uniform
   C2<T>* lds = exch + team * lds_elems(P);
   const T scale = (T)1 / ((T)ph * (T)P);
   const C2<T>* zrow = Z + beta * z_angle_stride + z_row_offset<T, P>(i);

@@ -45,6 +45,12 @@ __device__ __forceinline__ int row_out_pos(int lane, int q) {
   else return lane + TEAM * q;
 }
 
+// Both input layouts (lane + TEAM q, and the split one) are q-major: the
+// positions k < P/2 are exactly those with q < R/2, k = 0 can only occur at
+// q = 0 and k = P/2 only at q = R/2.  The helpers below branch on q (a
+// compile-time constant after unrolling) and select per lane only at those
+// two positions, so no lane-divergent branch is left.
+
 // Raw loads of row i of pairs p0 (and p1 when has1): element k of the half
 // spectrum that sequence index k (row_in_pos) needs (its mirror P - k in the
 // upper half; slot 0 for k = 0 and k = P/2).
@@ -57,11 +63,12 @@ __device__ __forceinline__ void load_raw(const C2<T>* __restrict__ z0,
   constexpr int R = P / TEAM;
   constexpr int TW = tile_width<T>();
   constexpr int HALF = P / 2;
+  static_assert(R % 2 == 0, "two halves of positions per lane");
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int k = row_in_pos<TEAM, SPLIT>(lane, q);
-    const int kk = k > HALF ? P - k : k;
-    const int e = kk == HALF ? 0 : kk;
+    int e = q < R / 2 ? k : P - k;              // k <= P/2 - 1, or its mirror
+    if (q == R / 2) e = e == HALF ? 0 : e;      // k = P/2 sits in slot 0
     const int off = (e / TW) * tile_stride + (e % TW);
     u0[q] = z0[off];
     u1[q] = has1 ? z1[off] : mk<T>((T)0, (T)0);
@@ -78,16 +85,18 @@ __device__ __forceinline__ void build_pack(const C2<T> (&u0)[P / TEAM],
   constexpr int HALF = P / 2;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int k = row_in_pos<TEAM, SPLIT>(lane, q);
-    const int kk = k > HALF ? P - k : k;
-    if (kk == 0)
-      w[q] = mk<T>(u0[q].x, u1[q].x);
-    else if (kk == HALF)
-      w[q] = mk<T>(u0[q].y, u1[q].y);
-    else if (k < HALF)
-      w[q] = mk<T>(u0[q].x - u1[q].y, u0[q].y + u1[q].x);  // u0 + i u1
-    else
-      w[q] = mk<T>(u0[q].x + u1[q].y, u1[q].x - u0[q].y);  // conj(u0) + i conj(u1)
+    if (q < R / 2) {
+      // u0 + i u1 (k = 0: the real k_x = 0 values packed in slot 0)
+      C2<T> g = mk<T>(u0[q].x - u1[q].y, u0[q].y + u1[q].x);
+      if (q == 0 && row_in_pos<TEAM, SPLIT>(lane, q) == 0) g = mk<T>(u0[q].x, u1[q].x);
+      w[q] = g;
+    } else {
+      // conj(u0) + i conj(u1) (k = P/2: the k_x = P/2 values of slot 0)
+      C2<T> g = mk<T>(u0[q].x + u1[q].y, u1[q].x - u0[q].y);
+      if (q == R / 2 && row_in_pos<TEAM, SPLIT>(lane, q) == HALF)
+        g = mk<T>(u0[q].y, u1[q].y);
+      w[q] = g;
+    }
   }
 }
 
