@@ -53,7 +53,8 @@ k_fwd_rows(const uint8_t* __restrict__ lab, const uint8_t* __restrict__ msk,
     if (msk) msk += beta * src_stride;
   }
   const int nteams = blockDim.x / TEAM;
-  const int team = threadIdx.x / TEAM;
+  static_assert(TEAM % 64 == 0, "teams of whole waves");
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / TEAM);  // wave-uniform
   const int lane = threadIdx.x % TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
 
@@ -179,7 +180,8 @@ k_fwd_cols(const C2<T>* __restrict__ xrow, int H, long long x_angle_stride,
   const int t = blockIdx.x / NPART, part = blockIdx.x % NPART;
   const int lbl = blockIdx.y, beta = blockIdx.z;
   if (gate != nullptr && gate[beta] == 0u) return;
-  const int team = threadIdx.x / TEAM;
+  static_assert(TEAM % 64 == 0, "teams of whole waves");
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / TEAM);  // wave-uniform
   const int lane = threadIdx.x % TEAM;
   const C2<T>* src = xrow + beta * x_angle_stride + lbl * x_label_stride +
                      (long long)t * H * TW;

@@ -257,7 +257,8 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     z_base = Z + (long long)(t / NPART) * z_tile_stride_rt<T>(sh, zg);
   }
   const int a0 = ablk * BA;
-  const int team = threadIdx.x / TEAM;
+  static_assert(TEAM % 64 == 0, "teams of whole waves");
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / TEAM);  // wave-uniform
   const int lane = threadIdx.x % TEAM;
   const int part = t % NPART;
   const int c = (t / NPART) * TW + part * CPW + team;
