@@ -41,7 +41,10 @@ def _same(r, ref):
     ((100, 90, 80, 110), (4, 12), "fp32", FORCE),
     ((300, 260, 280, 310), (8, 8), "fp32", 0),
     ((160, 150, 170, 140), (6, 5), "fp64", 0),
-], ids=["fp32-q4x12", "fp32-forced-rerun", "fp32-p768", "fp64"])
+    # 4096-point rows (two workgroups per map row): every row shape the
+    # tuner times, the spilling 1024-lane one included, must agree too
+    ((40, 1100, 36, 1000), (4, 5), "fp32", 0),
+], ids=["fp32-q4x12", "fp32-forced-rerun", "fp32-p768", "fp64", "fp32-rows4096"])
 def test_tuned_plan_matches_default(gpu, oracle, tmp_path, size, q, prec, flags):
     cm, torch = gpu
     ha, wa, hb, wb = size
