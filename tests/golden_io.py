@@ -1,7 +1,8 @@
 """Reader of the hand-worked fixtures in tests/golden/.
 
-Each fixture is plain text: the label counts, the images and masks, one
-`shift` line per displacement of the map (dy, dx, N, the joint counts C_ab in
+Each fixture is plain text: the label counts, the images and masks (or, for
+the spatially weighted examples `swmi_*`, per-pixel weights), one `shift`
+line per displacement of the map (dy, dx, N, the joint counts C_ab in
 row-major (a, b) order, MI as a closed form in numbers, + - * / ( ) and
 log2), and `argmax` lines (gamma, dy, dx) for Alg. 1's choice.  The values
 were derived by hand from the paper's definitions; each file states the
@@ -19,8 +20,11 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 _CLOSED_FORM = re.compile(r"^[0-9.+\-*/()]*(log2\([0-9.+\-*/]+\)[0-9.+\-*/()]*)*$")
 
 
-def fixtures():
-    return sorted(f for f in os.listdir(GOLDEN) if f.endswith(".txt"))
+def fixtures(kind: str = "cmif"):
+    """Fixture files of one kind: "cmif" (labels and masks) or "swmi"
+    (labels and weights)."""
+    return sorted(f for f in os.listdir(GOLDEN)
+                  if f.startswith(kind + "_") and f.endswith(".txt"))
 
 
 def closed_form(s: str) -> float:
@@ -41,14 +45,17 @@ def load(name: str) -> dict:
         t = ln.split()
         if t[0] == "labels":
             fx["qa"], fx["qb"] = int(t[1]), int(t[2])
-        elif t[0] in ("image", "mask"):
+        elif t[0] in ("image", "mask", "weight"):
             h, w = int(t[2]), int(t[3])
-            rows = [[int(v) for v in next(it).split()] for _ in range(h)]
-            arr = np.array(rows, np.uint8)
+            rows = [next(it).split() for _ in range(h)]
+            arr = (np.array(rows, np.float64) if t[0] == "weight"
+                   else np.array([[int(v) for v in r] for r in rows], np.uint8))
             assert arr.shape == (h, w), (name, ln)
-            fx[("" if t[0] == "image" else "M") + t[1]] = arr
+            fx[{"image": "", "mask": "M", "weight": "W"}[t[0]] + t[1]] = arr
         elif t[0] == "shift":
             q = fx["qa"] * fx["qb"]
+            # weighted examples list weighted counts (exact here: integer
+            # weights), label examples pixel counts
             dy, dx, n = int(t[1]), int(t[2]), int(t[3])
             c = np.array([int(v) for v in t[4:4 + q]], np.int64)
             fx["shifts"].append(dict(dy=dy, dx=dx, n=n,
