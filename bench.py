@@ -418,8 +418,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not "
-              "supported (angles would be sharded across GPUs with one "
-              "all-gather of the per-GPU best; not part of this build)",
+              "supported (the library runs on one GPU; sharding the angles "
+              "across GPUs with one all-gather of the per-GPU best is not "
+              "implemented)",
               file=sys.stderr)
         sys.exit(2)
 
