@@ -427,8 +427,9 @@ typedef struct cmif_plan_info {
   int32_t rows_per_wg;        /* pair row kernel: map rows per workgroup */
   int32_t labels_per_team;    /* pair row kernel: labels of B per team (0:
                                  the default shape) */
-  int32_t xcd_grouping;       /* pair column kernel: XCD-grouped order (1)
-                                 or launch order (0, the default) */
+  int32_t xcd_grouping;       /* pair column kernel: XCD-grouped order (1,
+                                 the default when every column length is a
+                                 power of two) or launch order (0) */
   int32_t tuned;              /* 0 default shapes, 1 timed, 2 from the cache */
   int32_t tune_runs;          /* eager passes spent timing candidates */
   int32_t cols_half;          /* pair column kernel: half the default columns

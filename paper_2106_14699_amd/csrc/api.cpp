@@ -1520,10 +1520,15 @@ cmif_status cmif_plan(const cmif_plan_desc* d, cmif_plan_t* out) {
   size_t smax = 0;
   for (const auto& g : P->pairs) smax = std::max(smax, layout_for(*P, g).end);
   P->scratch_bytes = smax;
-  // default column order: launch order (with Z's non-temporal stores and
-  // interleaved pairs the XCD-grouped order measured 1-10 % slower at every
-  // size and precision; it stays a tuner candidate)
-  P->def_xcd = 0;
+  // default column order: XCD-grouped (each tile's label-a workgroups on
+  // one XCD, reading its F_B columns from that L2 in rotated label order)
+  // where every column length is a power of two; measured against launch
+  // order per call: 0.90 (512 points), 0.91-0.98 (1024, FP64 / FP32),
+  // 0.99-1.00 (2048).  At 3 * 2^k lengths launch order stays the default
+  // (the XCD order measured 1.5-2.4 % slower at 768).  The tuner times both.
+  bool pow2_cols = true;
+  for (const PairPlan& g : P->pairs) pow2_cols = pow2_cols && is_pow2(g.ph);
+  P->def_xcd = pow2_cols ? 1 : 0;
   P->xcd = P->def_xcd;
   // rows per workgroup: 2 for FP32 1024-point rows (2-4 % faster there), 1
   // elsewhere (FP64 and 2048-point rows measured 2-5 % slower with 2, and

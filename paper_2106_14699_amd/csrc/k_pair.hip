@@ -113,18 +113,24 @@ __device__ __forceinline__ void pair_cols_store(C2<T> (&v)[P / TEAM], C2<T>* sme
 // Runs labels b in [b_begin, b_end) of B against labels a0 .. a0 + BA - 1
 // of A (those below QA; pair blocking: each F_B column read serves BA
 // products); the output slot of (a, b) is a * QB + b, or zpair0 for the one
-// pair of an item (BA = 1).
+// pair of an item (BA = 1).  The b loop starts at b_begin + rot and wraps
+// (every pair is computed on its own, so the order changes no result).
 template <typename T, int P, int TEAM, int CPW, int BA, class TWS>
 __device__ __forceinline__ void pair_cols_run(
     const C2<T>* __restrict__ fa_col, long long fa_label_stride, int a0, int QA,
     int QB, const C2<T>* __restrict__ fb_base, long long fb_label_stride,
-    int b_begin, int b_end, int zpair0, int ha, int hb, int sh,
+    int b_begin, int b_end, int rot, int zpair0, int ha, int hb, int sh,
     C2<T>* __restrict__ z_base, long long z_pair_stride, const TWS& ftw,
     C2<T>* smem, int c, int team, int part, int lane, int zg) {
   constexpr int R = P / TEAM;
   C2<T>* lds = smem + team * lds_elems(P);
   auto slot = [&](int ab, int b) {
     return zpair0 >= 0 ? zpair0 : (a0 + ab) * QB + b;
+  };
+  const int nbl = b_end - b_begin;
+  auto b_at = [&](int k) {  // k-th label of the rotated order
+    const int j = k + rot;
+    return b_begin + (j >= nbl ? j - nbl : j);
   };
   if (fa_col == nullptr) {
     // the B operand already holds the product spectra of every pair,
@@ -152,16 +158,17 @@ __device__ __forceinline__ void pair_cols_run(
     // software pipeline: the next b's column is in flight during this FFT
     C2<T> fbn[R];
     {
-      const C2<T>* fb0 = fb_base + b_begin * fb_label_stride;
+      const C2<T>* fb0 = fb_base + b_at(0) * fb_label_stride;
 #pragma unroll
       for (int q = 0; q < R; ++q) fbn[q] = fb0[lane + TEAM * q];
     }
-    for (int b = b_begin; b < b_end; ++b) {
+    for (int k = 0; k < nbl; ++k) {
+      const int b = b_at(k);
       C2<T> fb[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) fb[q] = fbn[q];
-      if (b + 1 < b_end) {
-        const C2<T>* fb_next = fb_base + (b + 1) * fb_label_stride;
+      if (k + 1 < nbl) {
+        const C2<T>* fb_next = fb_base + b_at(k + 1) * fb_label_stride;
 #pragma unroll
         for (int q = 0; q < R; ++q) fbn[q] = fb_next[lane + TEAM * q];
       }
@@ -179,7 +186,8 @@ __device__ __forceinline__ void pair_cols_run(
     }
   } else {
     // slot 0 packs the k_x = 0 and k_x = P_w/2 columns (both Hermitian)
-    for (int b = b_begin; b < b_end; ++b) {
+    for (int k = 0; k < nbl; ++k) {
+      const int b = b_at(k);
       const C2<T>* fb_col = fb_base + b * fb_label_stride;
 #pragma unroll
       for (int ab = 0; ab < BA; ++ab) {
@@ -222,7 +230,7 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
   constexpr int TW = tile_width<T>();
   constexpr int NPART = TW / CPW;  // workgroups per tile
   int t = blockIdx.x;  // tile part: tile t / NPART, part t % NPART
-  int ablk, beta, b_begin, b_end, zpair0;
+  int ablk, beta, b_begin, b_end, zpair0, rot = 0;
   C2<T>* z_base;
   if (items == nullptr) {
     // all pairs: workgroup (tile, block of BA labels of A, angle) runs every b
@@ -241,6 +249,11 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     }
     b_begin = 0;
     b_end = QB;
+    // XCD-grouped order: the Q_A workgroups of a tile run at the same time
+    // on one XCD; each starts its b loop at its own label, so that they read
+    // different F_B columns of the tile (all of it stays in that L2) rather
+    // than the same lines at once
+    rot = xcd_groups ? ablk % QB : 0;
     zpair0 = -1;
     z_base = Z + beta * z_angle_stride + (long long)(t / NPART) * z_tile_stride_rt<T>(sh, zg);
   } else {
@@ -271,14 +284,14 @@ k_pair_cols(const C2<T>* __restrict__ FA, long long fa_label_stride,
     __syncthreads();
     const FftTwTable<T, P, TEAM, MAXR> ftw{twl};
     pair_cols_run<T, P, TEAM, CPW, BA>(fa_col, fa_label_stride, a0, QA, QB, fb_base,
-                                       fb_label_stride, b_begin, b_end, zpair0, ha, hb,
+                                       fb_label_stride, b_begin, b_end, rot, zpair0, ha, hb,
                                        sh, z_base, z_pair_stride, ftw, smem, c, team,
                                        part, lane, zg);
   } else {
     FftTw<T, P, TEAM, MAXR> ftw;
     fft_load_twiddles<T, P, TEAM, 1, MAXR>(ftw, tw, lane);
     pair_cols_run<T, P, TEAM, CPW, BA>(fa_col, fa_label_stride, a0, QA, QB, fb_base,
-                                       fb_label_stride, b_begin, b_end, zpair0, ha, hb,
+                                       fb_label_stride, b_begin, b_end, rot, zpair0, ha, hb,
                                        sh, z_base, z_pair_stride, ftw, smem, c, team,
                                        part, lane, zg);
   }

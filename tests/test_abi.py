@@ -289,8 +289,9 @@ def test_autotune_plan_and_cache_file(cm, tmp_path):
     # no file: default shapes, not yet tuned
     info = _tune_plan(cm, None)
     assert (info["tuned"], info["tune_runs"]) == (0, 0)
+    # power-of-two column length (128): the XCD-grouped column order
     assert (info["rows_per_wg"], info["labels_per_team"], info["xcd_grouping"]) \
-        == (1, 0, 0)
+        == (1, 0, 1)
     assert (info["cols_half"], info["cols_maxr"], info["cols_ba"]) == (0, 16, 1)
     ph, pw = info["fft_h"], info["fft_w"]
     key = (f"cmif-tune v1 gfx950 {ph}x{pw}:127x127 qa=4 qb=4 prec=0 "

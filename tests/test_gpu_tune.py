@@ -100,11 +100,12 @@ def test_tuned_plan_matches_default(gpu, oracle, tmp_path, size, q, prec, flags)
 @pytest.mark.parametrize("size", [(400, 400, 400, 400), (300, 260, 280, 310)],
                          ids=["fft1024", "fft768"])
 def test_every_column_shape_matches_default(gpu, tmp_path, size):
-    """Each FP32 column-pass shape (half or whole tile of columns per
-    workgroup x radix cap 16 or 8 x one or two labels of A per workgroup),
-    forced through the tune cache, gives the default shape's counts, N and
-    digests bit for bit and the same MI bitwise (the row pass sums the same
-    integers in the same order)."""
+    """Each FP32 column-pass shape (launch or XCD-grouped workgroup order,
+    the latter with each workgroup's labels b rotated x half or whole tile of
+    columns per workgroup x radix cap 16 or 8 x one or two labels of A per
+    workgroup), forced through the tune cache, gives the default shape's
+    counts, N and digests bit for bit and the same MI bitwise (the row pass
+    sums the same integers in the same order)."""
     import itertools
     cm, torch = gpu
     ha, wa, hb, wb = size
@@ -118,16 +119,17 @@ def test_every_column_shape_matches_default(gpu, tmp_path, size):
     sh, sw = ha + hb - 1, wa + wb - 1
     key = (f"cmif-tune v1 gfx950 {info['fft_h']}x{info['fft_w']}:{sh}x{sw} "
            f"qa={q} qb={q} prec=0 batch={info['angle_batch']}")
-    for half, maxr, ba in itertools.product((0, 1), (16, 8), (1, 2)):
-        f = tmp_path / f"tune_{half}_{maxr}_{ba}.txt"
-        f.write_text(f"{key} rows_per_wg=1 bpw=0 xcd=0 half={half} maxr={maxr} "
+    for xcd, half, maxr, ba in itertools.product((0, 1), (0, 1), (16, 8), (1, 2)):
+        f = tmp_path / f"tune_{xcd}_{half}_{maxr}_{ba}.txt"
+        f.write_text(f"{key} rows_per_wg=1 bpw=0 xcd={xcd} half={half} maxr={maxr} "
                      f"ba={ba}\n")
         plan = cm.Plan([size], q, q, angles=angles, flags=AUTOTUNE,
                        tune_cache_path=str(f))
         pi = plan.info()
         assert pi["tuned"] == 2
-        assert (pi["cols_half"], pi["cols_maxr"], pi["cols_ba"]) == (half, maxr, ba)
-        say(f"[gpu] column shape half={half} maxr={maxr} ba={ba} {size}")
+        assert (pi["xcd_grouping"], pi["cols_half"], pi["cols_maxr"],
+                pi["cols_ba"]) == (xcd, half, maxr, ba)
+        say(f"[gpu] column shape xcd={xcd} half={half} maxr={maxr} ba={ba} {size}")
         r = _run(plan, ins)
         for name in ("n", "counts", "digest"):
             g = r[name][0].cpu().numpy()
