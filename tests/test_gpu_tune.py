@@ -97,33 +97,35 @@ def test_tuned_plan_matches_default(gpu, oracle, tmp_path, size, q, prec, flags)
         assert abs(mi[i, j] - mo) <= MI_TOL, (i, j)
 
 
-@pytest.mark.parametrize("size", [(400, 400, 400, 400), (300, 260, 280, 310)],
-                         ids=["fft1024", "fft768"])
-def test_every_column_shape_matches_default(gpu, tmp_path, size):
+@pytest.mark.parametrize("size,qa,qb", [((400, 400, 400, 400), 4, 4),
+                                        ((300, 260, 280, 310), 4, 4),
+                                        ((400, 400, 400, 400), 3, 5)],
+                         ids=["fft1024", "fft768", "fft1024-q3x5"])
+def test_every_column_shape_matches_default(gpu, tmp_path, size, qa, qb):
     """Each FP32 column-pass shape (launch or XCD-grouped workgroup order,
     the latter with each workgroup's labels b rotated x half or whole tile of
     columns per workgroup x radix cap 16 or 8 x one or two labels of A per
     workgroup), forced through the tune cache, gives the default shape's
     counts, N and digests bit for bit and the same MI bitwise (the row pass
-    sums the same integers in the same order)."""
+    sums the same integers in the same order).  An odd Q_B makes the rotated
+    label order wrap at an odd length."""
     import itertools
     cm, torch = gpu
     ha, wa, hb, wb = size
-    q = 4
     angles = [0.0, math.radians(70.0)]
-    c = synth.random_case(7300 + ha, ha, wa, hb, wb, q, q, mask_density=0.8)
+    c = synth.random_case(7300 + ha + qb, ha, wa, hb, wb, qa, qb, mask_density=0.8)
     ins = [dev(torch, c[k]) for k in ("A", "MA", "B", "MB")]
-    base = cm.Plan([size], q, q, angles=angles)
+    base = cm.Plan([size], qa, qb, angles=angles)
     ref = _run(base, ins)
     info = base.info()
     sh, sw = ha + hb - 1, wa + wb - 1
     key = (f"cmif-tune v1 gfx950 {info['fft_h']}x{info['fft_w']}:{sh}x{sw} "
-           f"qa={q} qb={q} prec=0 batch={info['angle_batch']}")
+           f"qa={qa} qb={qb} prec=0 batch={info['angle_batch']}")
     for xcd, half, maxr, ba in itertools.product((0, 1), (0, 1), (16, 8), (1, 2)):
         f = tmp_path / f"tune_{xcd}_{half}_{maxr}_{ba}.txt"
         f.write_text(f"{key} rows_per_wg=1 bpw=0 xcd={xcd} half={half} maxr={maxr} "
                      f"ba={ba}\n")
-        plan = cm.Plan([size], q, q, angles=angles, flags=AUTOTUNE,
+        plan = cm.Plan([size], qa, qb, angles=angles, flags=AUTOTUNE,
                        tune_cache_path=str(f))
         pi = plan.info()
         assert pi["tuned"] == 2
